@@ -1,0 +1,193 @@
+"""ctypes front end of the CPU oracle (kgref.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the GPU library.  It builds
+``libkgref.so`` with gcc on first use if it is missing or older than its
+source.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kgref.c")
+LIB = os.path.join(HERE, "libkgref.so")
+
+GNM, GNP = 0, 1
+TAG_DTREE, TAG_UTREE, TAG_CBIN, TAG_TTREE, TAG_TLEAF, TAG_INST = 1, 2, 3, 4, 5, 6
+
+
+def build(force=False):
+    """Compile the oracle: plain C11, IEEE binary64 without FMA contraction."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class Inst(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("p", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("model", ctypes.c_uint32),
+                ("directed", ctypes.c_uint32), ("P", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        u64, u32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
+        vp = ctypes.c_void_p
+        ip = ctypes.POINTER(Inst)
+        L.kgref_philox.argtypes = [vp, vp, vp]
+        L.kgref_log.argtypes = [dbl]; L.kgref_log.restype = dbl
+        L.kgref_log1p.argtypes = [dbl]; L.kgref_log1p.restype = dbl
+        L.kgref_lnf.argtypes = [u64]; L.kgref_lnf.restype = dbl
+        L.kgref_lnf_diff.argtypes = [u64, u64]; L.kgref_lnf_diff.restype = dbl
+        L.kgref_hyp.argtypes = [u64, u64, u64, u64, u32, u32, u32]; L.kgref_hyp.restype = u64
+        L.kgref_bin.argtypes = [u64, dbl, u64, u32, u32, u32]; L.kgref_bin.restype = u64
+        L.kgref_validate.argtypes = [ip]; L.kgref_validate.restype = ctypes.c_int
+        L.kgref_tile_exponent.argtypes = [ip]; L.kgref_tile_exponent.restype = u32
+        L.kgref_num_chunks.argtypes = [ip]; L.kgref_num_chunks.restype = u64
+        L.kgref_chunk_counts.argtypes = [ip, vp]; L.kgref_chunk_counts.restype = ctypes.c_int
+        L.kgref_chunk_count_path.argtypes = [ip, u64]; L.kgref_chunk_count_path.restype = u64
+        L.kgref_chunk_num_tiles.argtypes = [ip, u64]; L.kgref_chunk_num_tiles.restype = u64
+        L.kgref_tile_counts.argtypes = [ip, u64, u64, vp]; L.kgref_tile_counts.restype = u64
+        L.kgref_leaf.argtypes = [u64, u64, u64, u32, u32, vp]; L.kgref_leaf.restype = ctypes.c_int
+        L.kgref_chunk_edges.argtypes = [ip, u64, vp]; L.kgref_chunk_edges.restype = ctypes.c_int64
+        L.kgref_chunk_edges_given.argtypes = [ip, u64, u64, vp]
+        L.kgref_chunk_edges_given.restype = ctypes.c_int64
+        L.kgref_generate.argtypes = [ip, vp, u64, ctypes.c_int]; L.kgref_generate.restype = ctypes.c_int64
+        L.kgref_instance_seed.argtypes = [u64, u32]; L.kgref_instance_seed.restype = u64
+        L.kgref_max_threads.argtypes = []; L.kgref_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def inst(n, m=0, p=0.0, directed=True, seed=1, chunks=1, model=None):
+    if model is None:
+        model = GNP if (p and not m) else GNM
+    return Inst(int(n), int(m), float(p), int(seed) & (2**64 - 1), int(model), int(bool(directed)),
+                int(chunks), 0)
+
+
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().kgref_philox(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def log(x):
+    return lib().kgref_log(float(x))
+
+
+def log1p(x):
+    return lib().kgref_log1p(float(x))
+
+
+def lnf(k):
+    return lib().kgref_lnf(int(k))
+
+
+def lnf_diff(x, y):
+    return lib().kgref_lnf_diff(int(x), int(y))
+
+
+def hyp(N, K, k, seed, a=0, b=0, tag=TAG_DTREE):
+    return lib().kgref_hyp(int(N), int(K), int(k), int(seed) & (2**64 - 1), a, b, tag)
+
+
+def bin(N, p, seed, a=0, b=0, tag=TAG_CBIN):  # noqa: A001 - mirrors the variate's name
+    return lib().kgref_bin(int(N), float(p), int(seed) & (2**64 - 1), a, b, tag)
+
+
+def validate(I):
+    return lib().kgref_validate(ctypes.byref(I))
+
+
+def tile_exponent(I):
+    return lib().kgref_tile_exponent(ctypes.byref(I))
+
+
+def num_chunks(I):
+    return lib().kgref_num_chunks(ctypes.byref(I))
+
+
+def chunk_counts(I):
+    C = num_chunks(I)
+    out = np.zeros(C, dtype=np.uint64)
+    st = lib().kgref_chunk_counts(ctypes.byref(I), _ptr(out))
+    if st:
+        raise ValueError("kgref_chunk_counts status %d" % st)
+    return out
+
+
+def chunk_count_path(I, c):
+    return lib().kgref_chunk_count_path(ctypes.byref(I), int(c))
+
+
+def tile_counts(I, c, Kc):
+    T = lib().kgref_chunk_num_tiles(ctypes.byref(I), int(c))
+    out = np.zeros(max(T, 1), dtype=np.uint64)
+    lib().kgref_tile_counts(ctypes.byref(I), int(c), int(Kc), _ptr(out))
+    return out[:T]
+
+
+def leaf(k, St, seed, ordinal, tile):
+    out = np.zeros(max(int(k), 1), dtype=np.uint64)
+    st = lib().kgref_leaf(int(k), int(St), int(seed) & (2**64 - 1), int(ordinal), int(tile), _ptr(out))
+    if st:
+        raise ValueError("kgref_leaf status %d" % st)
+    return out[:int(k)]
+
+
+def chunk_edges(I, c, Kc=None):
+    if Kc is None:
+        Kc = chunk_count_path(I, c)
+    out = np.zeros((max(int(Kc), 1), 2), dtype=np.uint32)
+    r = lib().kgref_chunk_edges_given(ctypes.byref(I), int(c), int(Kc), _ptr(out))
+    if r < 0:
+        raise ValueError("kgref_chunk_edges status %d" % r)
+    return out[:r]
+
+
+def generate(I, threads=0, cap=None):
+    """Whole edge list as an (E, 2) uint32 array."""
+    if cap is None:
+        cap = int(chunk_counts(I).sum())
+    out = np.zeros((max(cap, 1), 2), dtype=np.uint32)
+    r = lib().kgref_generate(ctypes.byref(I), _ptr(out), cap, int(threads))
+    if r < 0:
+        raise ValueError("kgref_generate status %d" % r)
+    return out[:r]
+
+
+def generate_into(I, out, threads=0):
+    """Generate into a preallocated (cap, 2) uint32 array; returns the edge count."""
+    r = lib().kgref_generate(ctypes.byref(I), _ptr(out), out.shape[0], int(threads))
+    if r < 0:
+        raise ValueError("kgref_generate status %d" % r)
+    return r
+
+
+def instance_seed(base, i):
+    return lib().kgref_instance_seed(int(base) & (2**64 - 1), int(i))
+
+
+def max_threads():
+    return lib().kgref_max_threads()
