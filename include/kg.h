@@ -1,0 +1,152 @@
+/*
+ * kg.h -- C ABI of the MI355X generator for Erdos-Renyi graphs G(n,m) and
+ * G(n,p), directed or undirected, following the communication-free method of
+ * Funke et al., "Communication-free Massively Distributed Graph Generation"
+ * (arXiv 1710.07565, Sec. 4).
+ *
+ * Conventions shared by every entry point:
+ *   - Inputs are the problem as the paper states it: n vertices; m edges
+ *     (G(n,m), Sec. 2.1.1: a graph uniform among those with m edges) or a
+ *     probability p (G(n,p), Sec. 2.1.1: every slot independently); directed
+ *     or undirected; a seed; and the paper's P: the number of row chunks
+ *     (directed, Sec. 4.1) or of sections per matrix dimension (undirected,
+ *     Sec. 4.2, giving P(P+1)/2 chunks).
+ *   - Output edges are uint32 pairs [u0, v0, u1, v1, ...] in device memory.
+ *     Chunks come in canonical order (directed: rows ascending; undirected:
+ *     the upper-triangular chunk matrix row-major), each chunk ascending by
+ *     its local slot index.  Directed output is therefore sorted by (u, v);
+ *     undirected output always has u < v.
+ *   - The bytes are a pure function of (n, m or p, directed, seed, P): they do
+ *     not depend on the stream, the launch shape, tuning knobs or the device.
+ *   - Limits: n <= 2^32, slot count N = n(n-1) (directed) or n(n-1)/2
+ *     (undirected) below 2^53, 1 <= P <= n, P <= 2^31 directed, P <= 2^15
+ *     undirected.
+ *   - Every device pointer is owned by the caller; the library never frees
+ *     caller memory.  `stream` is a hipStream_t (NULL = default stream).
+ *     Calls are asynchronous on `stream` unless stated otherwise; argument
+ *     errors are returned synchronously and then nothing is enqueued.
+ *   - Scratch: each generation call takes a device workspace of at least the
+ *     size kg_workspace_bytes() reports.  Passing d_workspace = NULL makes the
+ *     library take it from the stream-ordered allocator (hipMallocAsync /
+ *     hipFreeAsync on `stream`).  Two calls in flight at once must not share
+ *     a workspace.
+ *   - Statuses are returned, never thrown across the ABI.
+ */
+#ifndef KG_H
+#define KG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kg_status;
+enum {
+    KG_OK = 0,
+    KG_EINVAL = -1,   /* bad argument: n, m, p, P, model, NULL pointer */
+    KG_ERANGE = -2,   /* outside the limits above */
+    KG_ENOSPC = -3,   /* output or workspace too small; nothing enqueued */
+    KG_EDEVICE = -4   /* a HIP call failed */
+};
+enum { KG_GNM = 0, KG_GNP = 1 };
+
+/* One graph instance.  `chunks` is the paper's P. */
+typedef struct {
+    uint64_t n;
+    uint32_t model;      /* KG_GNM or KG_GNP */
+    uint32_t directed;   /* 0 or 1 */
+    uint64_t m;          /* G(n,m) edge count */
+    double p;            /* G(n,p) edge probability in [0, 1] */
+    uint64_t seed;
+    uint32_t chunks;
+    uint32_t flags;      /* must be 0 */
+} kg_instance;
+
+/* Spec version of the output bits (changes whenever any output could). */
+uint32_t kg_spec_version(void);
+const char *kg_strerror(kg_status st);
+
+/* Device workspace needed by a call on `count` instances.  Host only. */
+kg_status kg_workspace_bytes(const kg_instance *inst, uint32_t count, uint64_t *bytes);
+
+/* G(n,m) (Sec. 4.1 directed, Sec. 4.2 undirected): writes exactly m edges to
+ * d_edges (room for capacity_edges pairs).  KG_ENOSPC if capacity < m. */
+kg_status kg_gnm(uint64_t n, uint64_t m, int directed, uint64_t seed, uint32_t chunks,
+                 uint32_t *d_edges, uint64_t capacity_edges,
+                 void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* G(n,p) (Sec. 4.3: binomial chunk counts keyed by chunk id, then the G(n,m)
+ * sampler per chunk).  The edge total is stored at the device address
+ * d_total (may be NULL).  If it exceeds capacity_edges nothing is written to
+ * d_edges; the caller detects this by reading *d_total after the stream
+ * completes. */
+kg_status kg_gnp(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks,
+                 uint32_t *d_edges, uint64_t capacity_edges, uint64_t *d_total,
+                 void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Edge total of a G(n,p) instance: runs only the count and offset steps and
+ * synchronises `stream`; *h_total is host memory. */
+kg_status kg_gnp_count(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks,
+                       uint64_t *h_total, void *d_workspace, uint64_t workspace_bytes,
+                       void *stream);
+
+/* Per-chunk edge counts of one instance (canonical order) into d_counts
+ * (device, one uint64 per chunk).  Asynchronous. */
+kg_status kg_chunk_counts(const kg_instance *inst, uint64_t *d_counts,
+                          void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Many instances in one pass over one arena.  Instance i is written at
+ * edge index d_inst_offsets[i] (device, count+1 entries, the last one the
+ * total), and its bytes equal those of kg_gnm / kg_gnp with the same
+ * arguments.  If the total exceeds arena_edges nothing is written to the
+ * arena (read d_inst_offsets[count] to see the need). */
+kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
+                   uint64_t arena_edges, uint64_t *d_inst_offsets,
+                   void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Per-instance seed of a batch drawn from a base seed: the Philox4x32-10
+ * image of counter (0, i, 0, 6) under key `base`, words (w1:w0). Host only. */
+uint64_t kg_instance_seed(uint64_t base, uint32_t i);
+
+/* Non-semantic launch knobs (never change output bits).  A value of 0
+ * restores the default.  Process-wide; set them before issuing calls. */
+enum {
+    KG_OPT_LEAF_CAP = 1,        /* samples a wave sorts in LDS per pass (128..1024) */
+    KG_OPT_SAMPLE_WAVES = 2,    /* resident sampler waves per compute unit (1..32) */
+    KG_OPT_PLAN_WAVES = 3,      /* resident tile-planner waves per compute unit (1..64) */
+    KG_OPT_TIME_KERNELS = 4     /* 1: bracket every kernel launch with hipEvents */
+};
+kg_status kg_set_option(int option, int64_t value);
+int64_t kg_get_option(int option);
+
+/* Kernel timing for measurement.  While KG_OPT_TIME_KERNELS is 1 every launch
+ * of kernel `kernel` (KG_KERNEL_*) is bracketed by two hipEvents recorded on
+ * the launch stream.  kg_kernel_time_read waits for the recorded events,
+ * returns the summed milliseconds and the number of launches, and forgets
+ * them.  Host only; synchronises with the recorded events. */
+enum { KG_KERNEL_COUNT = 0, KG_KERNEL_SCAN = 1, KG_KERNEL_PLAN = 2, KG_KERNEL_SAMPLE = 3 };
+kg_status kg_kernel_time_read(int kernel, double *ms_total, uint64_t *launches);
+
+/* Element-wise evaluation of the device building blocks, for checking them
+ * against an independent implementation.  d_in / d_out are device arrays of
+ * n records; the call is asynchronous on `stream`.
+ *   KG_EVAL_PHILOX    in: 6 x uint32 (c0 c1 c2 c3 k0 k1)   out: 4 x uint32
+ *   KG_EVAL_LOG       in: double x                          out: double log x
+ *   KG_EVAL_LOG1P     in: double x                          out: double log(1+x)
+ *   KG_EVAL_LNF_DIFF  in: 2 x uint64 (x, y)                 out: double ln y! - ln x!
+ *   KG_EVAL_HYP       in: 6 x uint64 (N, K, k, seed, a | b << 32, tag)  out: uint64
+ *   KG_EVAL_BIN       in: 6 x uint64 (N, p bits, 0, seed, a | b << 32, tag) out: uint64
+ *   KG_EVAL_SQRT_DIV  in: 2 x double (a, b)                 out: 2 x double (sqrt a, a / b)
+ * The variates follow Sec. 2.2 / 4.3 exactly as the generator uses them. */
+enum {
+    KG_EVAL_PHILOX = 1, KG_EVAL_LOG = 2, KG_EVAL_LOG1P = 3, KG_EVAL_LNF_DIFF = 4,
+    KG_EVAL_HYP = 5, KG_EVAL_BIN = 6, KG_EVAL_SQRT_DIV = 7
+};
+kg_status kg_eval(int fn, const void *d_in, void *d_out, uint64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KG_H */

@@ -912,3 +912,44 @@ int kgref_max_threads(void)
     return 1;
 #endif
 }
+
+/* Array evaluation of the building blocks for element-wise comparisons
+ * (record layouts as in the tests): fn 1 philox, 2 log, 3 log1p,
+ * 4 lnf_diff, 5 hyp, 6 bin. */
+void kgref_eval_many(int fn, const void *in, void *out, uint64_t n)
+{
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < (int64_t)n; i++) {
+        switch (fn) {
+        case 1: {
+            const uint32_t *r = (const uint32_t *)in + 6 * i;
+            kgref_philox(r, r + 4, (uint32_t *)out + 4 * i);
+            break;
+        }
+        case 2: ((double *)out)[i] = kgref_log(((const double *)in)[i]); break;
+        case 3: ((double *)out)[i] = kgref_log1p(((const double *)in)[i]); break;
+        case 4: {
+            const uint64_t *r = (const uint64_t *)in + 2 * i;
+            ((double *)out)[i] = kgref_lnf_diff(r[0], r[1]);
+            break;
+        }
+        case 5: {
+            const uint64_t *r = (const uint64_t *)in + 6 * i;
+            ((uint64_t *)out)[i] = kgref_hyp(r[0], r[1], r[2], r[3], (uint32_t)r[4], (uint32_t)(r[4] >> 32),
+                                             (uint32_t)r[5]);
+            break;
+        }
+        case 6: {
+            const uint64_t *r = (const uint64_t *)in + 6 * i;
+            double p;
+            memcpy(&p, &r[1], 8);
+            ((uint64_t *)out)[i] = kgref_bin(r[0], p, r[3], (uint32_t)r[4], (uint32_t)(r[4] >> 32),
+                                             (uint32_t)r[5]);
+            break;
+        }
+        default: break;
+        }
+    }
+}

@@ -69,6 +69,7 @@ def lib():
         L.kgref_generate.argtypes = [ip, vp, u64, ctypes.c_int]; L.kgref_generate.restype = ctypes.c_int64
         L.kgref_instance_seed.argtypes = [u64, u32]; L.kgref_instance_seed.restype = u64
         L.kgref_max_threads.argtypes = []; L.kgref_max_threads.restype = ctypes.c_int
+        L.kgref_eval_many.argtypes = [ctypes.c_int, vp, vp, u64]; L.kgref_eval_many.restype = None
         _lib = L
     return _lib
 
@@ -191,3 +192,13 @@ def instance_seed(base, i):
 
 def max_threads():
     return lib().kgref_max_threads()
+
+
+def eval_many(fn, records, out_dtype, out_width):
+    """Element-wise evaluation (fn: 1 philox, 2 log, 3 log1p, 4 lnf_diff,
+    5 hyp, 6 bin) over a contiguous record array."""
+    records = np.ascontiguousarray(records)
+    n = records.shape[0]
+    out = np.zeros((n, out_width), dtype=out_dtype)
+    lib().kgref_eval_many(int(fn), _ptr(records), _ptr(out), n)
+    return out

@@ -1,0 +1,184 @@
+"""MI355X generator for Erdos-Renyi graphs G(n,m) / G(n,p), directed or
+undirected, by the communication-free method of Funke et al. (arXiv
+1710.07565, Sec. 4).
+
+The Python layer only marshals arguments: device memory and streams come
+from PyTorch, every step of the generator runs in the HIP library
+``libkg.so`` (C ABI in include/kg.h).  Importing works without a GPU; calls
+need one and raise if the library has not been built.
+"""
+from dataclasses import dataclass
+
+from . import _lib
+from ._lib import KG_GNM, KG_GNP, KgError, KgInstance  # noqa: F401
+
+GNM, GNP = KG_GNM, KG_GNP
+
+
+@dataclass
+class Instance:
+    """One graph.  `chunks` is the paper's P: row chunks (directed, Sec. 4.1)
+    or sections per matrix dimension (undirected, Sec. 4.2)."""
+    n: int
+    model: int = GNM
+    directed: bool = True
+    m: int = 0
+    p: float = 0.0
+    seed: int = 1
+    chunks: int = 1
+
+    def c(self):
+        return KgInstance(int(self.n), int(self.model), int(bool(self.directed)), int(self.m), float(self.p),
+                          int(self.seed) & (2**64 - 1), int(self.chunks), 0)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def spec_version():
+    return _lib.lib().kg_spec_version()
+
+
+def instance_seed(base, i):
+    """Seed of instance i of a batch with base seed `base`."""
+    return _lib.lib().kg_instance_seed(int(base) & (2**64 - 1), int(i))
+
+
+def set_option(option, value):
+    _lib.check(_lib.lib().kg_set_option(int(option), int(value)), "kg_set_option")
+
+
+def get_option(option):
+    return _lib.lib().kg_get_option(int(option))
+
+
+def workspace_bytes(instances):
+    import ctypes
+    arr = (KgInstance * len(instances))(*[i.c() for i in instances])
+    out = ctypes.c_uint64(0)
+    _lib.check(_lib.lib().kg_workspace_bytes(arr, len(instances), ctypes.byref(out)), "kg_workspace_bytes")
+    return out.value
+
+
+def _workspace(instances, workspace, device):
+    torch = _torch()
+    need = workspace_bytes(instances)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    if workspace.numel() < need:
+        raise KgError(_lib.KG_ENOSPC, "workspace")
+    return workspace, need
+
+
+def gnm(n, m, directed=True, seed=1, chunks=1, out=None, workspace=None, stream=None, device="cuda"):
+    """Directed (Sec. 4.1) or undirected (Sec. 4.2) G(n,m): an (m, 2) uint32
+    tensor of edges on the device, in canonical chunk order."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((max(int(m), 0), 2), dtype=torch.uint32, device=device)
+    inst = Instance(n, GNM, directed, m, 0.0, seed, chunks)
+    ws, need = _workspace([inst], workspace, out.device)
+    st = _lib.lib().kg_gnm(int(n), int(m), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
+                           out.data_ptr() if out.numel() else None, out.shape[0], ws.data_ptr(), ws.numel(),
+                           _stream(stream))
+    _lib.check(st, "kg_gnm")
+    return out[:m]
+
+
+def gnp_count(n, p, directed=True, seed=1, chunks=1, workspace=None, stream=None, device="cuda"):
+    """Edge total of G(n,p) (synchronises the stream)."""
+    import ctypes
+    inst = Instance(n, GNP, directed, 0, p, seed, chunks)
+    ws, need = _workspace([inst], workspace, device)
+    tot = ctypes.c_uint64(0)
+    st = _lib.lib().kg_gnp_count(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
+                                 ctypes.byref(tot), ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(st, "kg_gnp_count")
+    return tot.value
+
+
+def gnp(n, p, directed=True, seed=1, chunks=1, out=None, total=None, workspace=None, stream=None,
+        device="cuda"):
+    """G(n,p) (Sec. 4.3).  Without `out` the exact size is found first with
+    gnp_count.  With `out`, returns (out, total) where total is a device
+    uint64 tensor; if total exceeds out.shape[0] nothing was written."""
+    torch = _torch()
+    inst = Instance(n, GNP, directed, 0, p, seed, chunks)
+    sized = out is None
+    if sized:
+        E = gnp_count(n, p, directed, seed, chunks, workspace=workspace, stream=stream, device=device)
+        out = torch.empty((E, 2), dtype=torch.uint32, device=device)
+    if total is None:
+        total = torch.zeros(1, dtype=torch.uint64, device=out.device)
+    ws, need = _workspace([inst], workspace, out.device)
+    st = _lib.lib().kg_gnp(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
+                           out.data_ptr() if out.numel() else None, out.shape[0], total.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(st, "kg_gnp")
+    if sized:
+        return out
+    return out, total
+
+
+def chunk_counts(inst, workspace=None, stream=None, device="cuda"):
+    """Per-chunk edge counts of one instance (uint64 device tensor)."""
+    torch = _torch()
+    from . import _lib as L
+    C = inst.chunks if inst.directed else inst.chunks * (inst.chunks + 1) // 2
+    out = torch.empty(C, dtype=torch.uint64, device=device)
+    ws, need = _workspace([inst], workspace, device)
+    st = L.lib().kg_chunk_counts(inst.c(), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    L.check(st, "kg_chunk_counts")
+    return out
+
+
+def batch(instances, arena=None, offsets=None, workspace=None, stream=None, device="cuda"):
+    """Generate many instances in one pass into one arena.  Returns
+    (arena, offsets): instance i occupies arena[offsets[i]:offsets[i+1]].
+    If the arena is too small nothing is written (offsets[-1] shows the need)."""
+    torch = _torch()
+    cnt = len(instances)
+    arr = (KgInstance * cnt)(*[i.c() for i in instances])
+    if arena is None:
+        total = 0
+        for i in instances:
+            if i.model == GNM:
+                total += int(i.m)
+            else:
+                total += gnp_count(i.n, i.p, i.directed, i.seed, i.chunks, stream=stream, device=device)
+        arena = torch.empty((total, 2), dtype=torch.uint32, device=device)
+    if offsets is None:
+        offsets = torch.empty(cnt + 1, dtype=torch.uint64, device=arena.device)
+    ws, need = _workspace(instances, workspace, arena.device)
+    st = _lib.lib().kg_batch(arr, cnt, arena.data_ptr() if arena.numel() else None, arena.shape[0],
+                             offsets.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(st, "kg_batch")
+    return arena, offsets
+
+
+def eval_device(fn, d_in, n, out_dtype, out_width, stream=None):
+    """Element-wise evaluation of a device building block (see kg_eval)."""
+    torch = _torch()
+    out = torch.empty((int(n), out_width), dtype=out_dtype, device=d_in.device)
+    st = _lib.lib().kg_eval(int(fn), d_in.data_ptr(), out.data_ptr(), int(n), _stream(stream))
+    _lib.check(st, "kg_eval")
+    return out
+
+
+def kernel_time_read(kernel):
+    """(summed ms, launches) of kernel `kernel` since the last read, from the
+    hipEvents the library records while KG_OPT_TIME_KERNELS is 1."""
+    import ctypes
+    ms, n = ctypes.c_double(0.0), ctypes.c_uint64(0)
+    _lib.check(_lib.lib().kg_kernel_time_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)),
+               "kg_kernel_time_read")
+    return ms.value, n.value

@@ -1,0 +1,494 @@
+// kg_device.hpp -- device building blocks of the generator: counter-based
+// random streams, the binary64 logarithm kernel, hypergeometric and binomial
+// variates, and the geometry of chunks, tiles and edge slots.
+//
+// Method: Funke et al., "Communication-free Massively Distributed Graph
+// Generation" (arXiv 1710.07565).  Every recursion node draws from its own
+// stream so that any chunk can recompute its sample size alone (Sec. 2.2);
+// sample sizes of sub-universes are hypergeometric (Sec. 2.2) or binomial
+// (Sec. 4.3); variates come from acceptance-rejection (Sec. 2.2).
+//
+// Bit reproducibility: only IEEE binary64 + - * / sqrt and exact conversions
+// are used, in a fixed order, with contraction disabled at build time
+// (-ffp-contract=off).  log is computed here from those operations; no
+// device math library routine decides a variate.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kg {
+
+// ---------------------------------------------------------------------------
+// Constants of the method
+// ---------------------------------------------------------------------------
+constexpr uint32_t kLambda = 512;       // expected samples per tile (sampling threshold)
+constexpr uint32_t kUnitTiles = 256;    // tiles a planner wave expands at once
+constexpr uint32_t kLnfTab = 1024;      // ln k! tabulated for k <= kLnfTab
+
+enum : uint32_t { TAG_DTREE = 1, TAG_UTREE = 2, TAG_CBIN = 3, TAG_TTREE = 4, TAG_TLEAF = 5, TAG_INST = 6 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplications with the bijection keyed by (k0, k1), bumped by the Weyl
+// constants between rounds.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__host__ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// A random stream: Philox keyed by the seed, counter (block, a, b, tag).
+struct Stream {
+    uint32_t k0, k1, a, b, tag;
+    __device__ __forceinline__ U4 block(uint32_t j) const { return philox(j, a, b, tag, k0, k1); }
+};
+
+__device__ __forceinline__ Stream make_stream(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag)
+{
+    return Stream{(uint32_t)seed, (uint32_t)(seed >> 32), a, b, tag};
+}
+
+// Sequential 64-bit draws: draw d is (w1:w0) of block d/2 if d is even,
+// (w3:w2) otherwise.
+struct Draws64 {
+    Stream s;
+    uint64_t next;
+    uint32_t cj;
+    U4 buf;
+    __device__ __forceinline__ explicit Draws64(const Stream &st) : s(st), next(0), cj(0xFFFFFFFFu), buf{0, 0, 0, 0} {}
+    __device__ __forceinline__ uint64_t get()
+    {
+        const uint64_t d = next++;
+        const uint32_t j = (uint32_t)(d >> 1);
+        if (j != cj) { buf = s.block(j); cj = j; }
+        return (d & 1) ? (((uint64_t)buf.w << 32) | buf.z) : (((uint64_t)buf.y << 32) | buf.x);
+    }
+};
+
+// Top 52 bits plus half an ulp: exact, strictly inside (0, 1).
+__device__ __forceinline__ double unit_of(uint64_t x)
+{
+    return ((double)(x >> 12) + 0.5) * 0x1p-52;
+}
+
+// Uniform integer in [0, R) by power-of-two mask and rejection.
+__device__ __forceinline__ uint64_t draw_below(Draws64 &d, uint64_t R)
+{
+    const uint64_t mask = R <= 1 ? 0ull : (~0ull >> __clzll(R - 1));
+    for (;;) {
+        const uint64_t x = d.get() & mask;
+        if (x < R) return x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Natural logarithm from + - * / (binary64).  x = 2^e f, f in [sqrt(1/2),
+// sqrt(2)); with u = f - 1 (exact) and s = u / (2 + u),
+//   log f = 2 atanh(s) = u - (u^2/2 - s (u^2/2 + R(s^2))),
+//   R(z) = sum_{i=1..11} 2 z^i / (2i + 1)  (Horner, innermost term first);
+// e ln 2 is added as e*hi (exact: hi has 32 fraction bits) and e*lo.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double atanh_series(double z)
+{
+    double r = 2.0 / 23.0;
+    r = 2.0 / 21.0 + z * r;
+    r = 2.0 / 19.0 + z * r;
+    r = 2.0 / 17.0 + z * r;
+    r = 2.0 / 15.0 + z * r;
+    r = 2.0 / 13.0 + z * r;
+    r = 2.0 / 11.0 + z * r;
+    r = 2.0 / 9.0 + z * r;
+    r = 2.0 / 7.0 + z * r;
+    r = 2.0 / 5.0 + z * r;
+    r = 2.0 / 3.0 + z * r;
+    return z * r;
+}
+
+__device__ __noinline__ double log_f64(double x)
+{
+    const double kLn2Hi = 0x1.62e42fee00000p-1;
+    const double kLn2Lo = 0x1.a39ef35793c76p-33;
+    const uint64_t bits = (uint64_t)__double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7ffu) - 1023;
+    const uint64_t mant = bits & 0x000FFFFFFFFFFFFFull;
+    uint64_t fb;
+    if (mant > 0x6A09E667F3BCDull) { fb = mant | (1022ull << 52); e += 1; }   // above sqrt(2)
+    else                           { fb = mant | (1023ull << 52); }
+    const double f = __longlong_as_double((long long)fb);
+    const double u = f - 1.0;
+    const double s = u / (2.0 + u);
+    const double z = s * s;
+    const double R = atanh_series(z);
+    const double hfsq = 0.5 * u * u;
+    const double dk = (double)e;
+    return dk * kLn2Hi - ((hfsq - (s * (hfsq + R) + dk * kLn2Lo)) - u);
+}
+
+__device__ __noinline__ double log1p_f64(double x)
+{
+    if (x > -0.25 && x < 0.25) {
+        const double s = x / (2.0 + x);
+        const double z = s * s;
+        const double R = atanh_series(z);
+        const double hfsq = 0.5 * x * x;
+        return x - (hfsq - s * (hfsq + R));
+    }
+    return log_f64(1.0 + x);
+}
+
+// ---------------------------------------------------------------------------
+// ln k!: table T[k] = T[k-1] + log k for k <= 1024 (built on the device by
+// kg_lnf_init_kernel); above it only differences are needed, from Stirling's
+// series with three correction terms in z = k + 1:
+//   lnf(a+d) - lnf(a) = (z - 1/2) log1p(d/z) + d (log(z + d) - 1)
+//                       + corr(z + d) - corr(z),
+//   corr(z) = 1/(12 z) - 1/(360 z^3) + 1/(1260 z^5),
+// so that two large log-factorials are never subtracted.
+// ---------------------------------------------------------------------------
+extern __device__ double g_lnf_tab[kLnfTab + 1];
+
+__device__ __forceinline__ double stirling_corr(double z)
+{
+    const double r = 1.0 / z;
+    const double r2 = r * r;
+    return r * (1.0 / 12.0 - r2 * (1.0 / 360.0 - r2 * (1.0 / 1260.0)));
+}
+
+__device__ __noinline__ double stirling_diff(uint64_t a, uint64_t d)
+{
+    const double z = (double)(a + 1);
+    const double zd = (double)(a + d + 1);
+    const double dd = (double)d;
+    const double t1 = (z - 0.5) * log1p_f64(dd / z);
+    const double t2 = dd * (log_f64(zd) - 1.0);
+    const double t3 = stirling_corr(zd) - stirling_corr(z);
+    return (t1 + t2) + t3;
+}
+
+// lnf(y) - lnf(x).
+__device__ __noinline__ double lnf_diff(uint64_t x, uint64_t y)
+{
+    if (x == y) return 0.0;
+    double sign = 1.0;
+    if (x > y) { const uint64_t t = x; x = y; y = t; sign = -1.0; }
+    double r;
+    if (y <= kLnfTab)      r = g_lnf_tab[y] - g_lnf_tab[x];
+    else if (x >= kLnfTab) r = stirling_diff(x, y - x);
+    else                   r = (g_lnf_tab[kLnfTab] - g_lnf_tab[x]) + stirling_diff(kLnfTab, y - kLnfTab);
+    return sign < 0.0 ? -r : r;
+}
+
+// floor(a * b / d) for a*b < 2^106, d >= 1, exactly: estimate in binary64,
+// correct with 128-bit products.
+__device__ __forceinline__ uint64_t muldiv_floor(uint64_t a, uint64_t b, uint64_t d)
+{
+    typedef unsigned __int128 u128;
+    const u128 num = (u128)a * b;
+    double est = floor(((double)a * (double)b) / (double)d);
+    uint64_t q = est <= 0.0 ? 0ull : (uint64_t)est;
+    while ((u128)q * d > num) --q;
+    while ((u128)(q + 1) * d <= num) ++q;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Discrete ratio of uniforms (Kinderman-Monahan; centre mu + 1/2 and
+// half-width (D1 sqrt(var + 1/2) + D2)/2 as in Stadlober's samplers).
+// Proposal j uses block j: U from (w1:w0), V from (w3:w2);
+// X = floor(a + h (V - 1/2) / U), accepted iff 2 log U <= log f(X)/f(M),
+// with the squeezes 4U - U^2 - 3 <= T (accept) and T <= U - 1/U (reject).
+// ---------------------------------------------------------------------------
+constexpr double kRouD1 = 0x1.b72cd3f331398p+0;   // 2 sqrt(2/e)
+constexpr double kRouD2 = 0x1.cc3ebd3bc711ap-1;   // 3 - 2 sqrt(3/e)
+
+// log f(x) - log f(M) of the hypergeometric law.
+struct HypRatio {
+    uint64_t N, K, k, M;
+    __device__ __forceinline__ double operator()(uint64_t X) const
+    {
+        double T = lnf_diff(X, M);
+        T = T + lnf_diff(k - X, k - M);
+        T = T + lnf_diff(K - X, K - M);
+        T = T + lnf_diff(N - K - k + X, N - K - k + M);
+        return T;
+    }
+};
+
+// log f(x) - log f(M) of the binomial law; lq = log p - log(1-p).
+struct BinRatio {
+    uint64_t N, M;
+    double lq;
+    __device__ __forceinline__ double operator()(uint64_t X) const
+    {
+        double T = lnf_diff(X, M);
+        T = T + lnf_diff(N - X, N - M);
+        T = T + ((double)X - (double)M) * lq;
+        return T;
+    }
+};
+
+template <class Ratio>
+__device__ __forceinline__ uint64_t rou_sample(const Stream &s, double a, double h, uint64_t upper,
+                                               const Ratio &ratio)
+{
+    const double upper_excl = (double)upper + 1.0;
+    for (uint32_t j = 0;; ++j) {
+        const U4 w = s.block(j);
+        const double U = unit_of(((uint64_t)w.y << 32) | w.x);
+        const double V = unit_of(((uint64_t)w.w << 32) | w.z);
+        const double t = a + h * (V - 0.5) / U;
+        if (!(t >= 0.0) || t >= upper_excl) continue;
+        const uint64_t X = (uint64_t)floor(t);
+        const double T = ratio(X);
+        if (U * (4.0 - U) - 3.0 <= T) return X;
+        if (U * (U - T) >= 1.0) continue;
+        if (2.0 * log_f64(U) <= T) return X;
+    }
+}
+
+// Hypergeometric: how many of k draws without replacement from N items land
+// among K marked ones (the sample size of a sub-universe, Sec. 2.2).
+__device__ __noinline__ uint64_t hyp(const Stream &s, uint64_t N, uint64_t K, uint64_t k)
+{
+    // symmetries: complement the draws, complement the marked set, swap roles
+    uint64_t k1 = k, K1 = K;
+    bool c1 = false, c2 = false;
+    if (k1 > N - k1) { k1 = N - k1; c1 = true; }
+    if (K1 > N - K1) { K1 = N - K1; c2 = true; }
+    const uint64_t lo = k1 < K1 ? k1 : K1;   // draws
+    const uint64_t hi = k1 < K1 ? K1 : k1;   // marked
+    uint64_t x;
+    if (lo == 0) {
+        x = 0;
+    } else if (lo <= 16) {
+        // direct simulation: the i-th draw picks one of the N - i items left
+        Draws64 d(s);
+        x = 0;
+        for (uint64_t i = 0; i < lo; ++i)
+            if (draw_below(d, N - i) < hi - x) ++x;
+    } else {
+        const double Nd = (double)N, Kd = (double)hi, kd = (double)lo;
+        const double pp = Kd / Nd;
+        const double mu = kd * pp;
+        const double var = (((Nd - kd) * kd) * pp) * (1.0 - pp) / (Nd - 1.0);
+        const double c = sqrt(var + 0.5);
+        const double h = kRouD1 * c + kRouD2;
+        const double a = mu + 0.5;
+        HypRatio r{N, hi, lo, muldiv_floor(lo + 1, hi + 1, N + 2)};
+        x = rou_sample(s, a, h, lo, r);
+    }
+    if (c2) x = k1 - x;
+    if (c1) x = K - x;
+    return x;
+}
+
+// Binomial(N, p): a G(n,p) chunk's edge count (Sec. 4.3).  Small means by
+// geometric waiting times floor(log U / log(1-p)); otherwise ratio of uniforms.
+__device__ __noinline__ uint64_t bin_core(const Stream &s, uint64_t N, double p)
+{
+    const double Nd = (double)N;
+    if (Nd * p < 16.0) {
+        const double L = log1p_f64(-p);
+        Draws64 d(s);
+        uint64_t X = 0, pos = 0;
+        for (;;) {
+            const double U = unit_of(d.get());
+            const double g = floor(log_f64(U) / L);
+            if (g >= (double)(N - pos)) return X;
+            pos += (uint64_t)g + 1;
+            ++X;
+        }
+    }
+    const double q = 1.0 - p;
+    const double mu = Nd * p;
+    const double var = mu * q;
+    const double c = sqrt(var + 0.5);
+    const double h = kRouD1 * c + kRouD2;
+    const double a = mu + 0.5;
+    BinRatio r{N, (uint64_t)floor((Nd + 1.0) * p), log_f64(p) - log1p_f64(-p)};
+    return rou_sample(s, a, h, N, r);
+}
+
+__device__ __forceinline__ uint64_t binom(const Stream &s, uint64_t N, double p)
+{
+    if (N == 0 || p <= 0.0) return 0;
+    if (p >= 1.0) return N;
+    if (p > 0.5) return N - bin_core(s, N, 1.0 - p);
+    return bin_core(s, N, p);
+}
+
+// ---------------------------------------------------------------------------
+// Instances and chunk geometry (Sec. 4.1 row chunks; Sec. 4.2 sections and
+// the upper-triangular chunk matrix, ordered row-major).
+// ---------------------------------------------------------------------------
+struct Inst {
+    uint64_t n, m;
+    double p;
+    uint64_t seed;
+    uint32_t model, directed, P, s;   // s: tile exponent, tiles of 2^s slots
+    uint64_t nchunks;                 // P (directed) or P(P+1)/2
+    uint64_t chunk_base;              // first global chunk index of the instance
+};
+
+__host__ __device__ __forceinline__ uint64_t section_bound(const Inst &I, uint64_t i)
+{
+    // floor(i n / P); i n < 2^64 because i <= P <= 2^31 and n <= 2^32
+    return (i * I.n) / I.P;
+}
+
+__host__ __device__ __forceinline__ uint64_t uord(uint64_t P, uint64_t i)
+{
+    return i * P - i * (i - 1) / 2;   // ordinal of diagonal chunk (i, i)
+}
+
+struct Chunk {
+    uint64_t N;       // slots
+    uint64_t row0;    // directed: first row
+    uint64_t a, h;    // undirected: row section start / size
+    uint64_t b, w;    // undirected: column section start / size
+    uint32_t diag;    // undirected triangle chunk
+};
+
+__device__ __forceinline__ Chunk chunk_geometry(const Inst &I, uint64_t c)
+{
+    Chunk g;
+    g.diag = 0; g.a = g.h = g.b = g.w = 0; g.row0 = 0;
+    if (I.directed) {
+        g.row0 = section_bound(I, c);
+        g.N = (section_bound(I, c + 1) - g.row0) * (I.n - 1);
+        return g;
+    }
+    // row of the chunk matrix: largest i with uord(i) <= c
+    uint64_t lo = 0, hi = I.P;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (uord(I.P, mid) <= c) lo = mid; else hi = mid;
+    }
+    const uint64_t ci = lo, cj = lo + (c - uord(I.P, lo));
+    g.a = section_bound(I, ci); g.h = section_bound(I, ci + 1) - g.a;
+    g.b = section_bound(I, cj); g.w = section_bound(I, cj + 1) - g.b;
+    g.diag = ci == cj;
+    g.N = g.diag ? g.h * (g.h - (g.h > 0)) / 2 : g.h * g.w;
+    return g;
+}
+
+// Tiles of chunk with N slots; planner units (subtrees of <= kUnitTiles
+// tiles): 2^d with d minimal such that ceil(T / 2^d) <= kUnitTiles.
+__device__ __forceinline__ uint64_t tiles_of(uint64_t N, uint32_t s)
+{
+    return (N + ((1ull << s) - 1)) >> s;
+}
+
+__device__ __forceinline__ uint32_t unit_depth(uint64_t T)
+{
+    uint32_t d = 0;
+    while (((T + (1ull << d) - 1) >> d) > kUnitTiles) ++d;
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// Chunk counts by walking one root-to-leaf path (what a single PE does in the
+// paper; Sec. 2.2, 4.1, 4.2).  The split of a range [lo, hi) of chunks or
+// sections is at lo + ceil((hi - lo)/2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t dtree_count(const Inst &I, uint64_t c)
+{
+    uint64_t k = I.m, lo = 0, hi = I.P;
+    uint32_t heap = 1;
+    const uint64_t w = I.n - 1;
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        const uint64_t blo = section_bound(I, lo);
+        const uint64_t Nn = (section_bound(I, hi) - blo) * w;
+        const uint64_t Nl = (section_bound(I, mid) - blo) * w;
+        const uint64_t X = hyp(make_stream(I.seed, heap, 0, TAG_DTREE), Nn, Nl, k);
+        if (c < mid) { hi = mid; k = X; heap = 2 * heap; }
+        else         { lo = mid; k = k - X; heap = 2 * heap + 1; }
+    }
+    return k;
+}
+
+__device__ __forceinline__ uint64_t tri_slots(const Inst &I, uint64_t a, uint64_t b)
+{
+    const uint64_t A = section_bound(I, b) - section_bound(I, a);
+    return A * (A - (A > 0)) / 2;
+}
+
+__device__ __forceinline__ uint64_t rect_slots(const Inst &I, uint64_t a, uint64_t b, uint64_t c, uint64_t d)
+{
+    return (section_bound(I, b) - section_bound(I, a)) * (section_bound(I, d) - section_bound(I, c));
+}
+
+__device__ __forceinline__ uint64_t utree_count(const Inst &I, uint64_t ci, uint64_t cj)
+{
+    uint64_t k = I.m, a = 0, b = I.P, cc = 0, d = 0;
+    uint32_t code = 1;
+    bool tri = true;
+    for (;;) {
+        if (tri) {
+            if (b - a == 1) return k;
+            const uint64_t l = a + (b - a + 1) / 2;
+            const uint64_t Nn = tri_slots(I, a, b), N1 = tri_slots(I, a, l), NR = rect_slots(I, a, l, l, b);
+            const uint64_t X0 = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, N1, k);
+            if (cj < l) { b = l; k = X0; code = 4 * code; continue; }
+            const uint64_t X1 = hyp(make_stream(I.seed, code, 1, TAG_UTREE), Nn - N1, NR, k - X0);
+            if (ci < l) { tri = false; cc = l; d = b; b = l; k = X1; code = 4 * code + 1; continue; }
+            a = l; k = k - X0 - X1; code = 4 * code + 2;
+            continue;
+        }
+        if (b - a == 1 && d - cc == 1) return k;
+        const uint64_t Nn = rect_slots(I, a, b, cc, d);
+        if (d - cc == 1) {
+            const uint64_t l = a + (b - a + 1) / 2;
+            const uint64_t X = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, rect_slots(I, a, l, cc, d), k);
+            if (ci < l) { b = l; k = X; code = 4 * code; }
+            else        { a = l; k = k - X; code = 4 * code + 1; }
+            continue;
+        }
+        if (b - a == 1) {
+            const uint64_t q = cc + (d - cc + 1) / 2;
+            const uint64_t X = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, rect_slots(I, a, b, cc, q), k);
+            if (cj < q) { d = q; k = X; code = 4 * code; }
+            else        { cc = q; k = k - X; code = 4 * code + 1; }
+            continue;
+        }
+        const uint64_t l = a + (b - a + 1) / 2, q = cc + (d - cc + 1) / 2;
+        const uint64_t N00 = rect_slots(I, a, l, cc, q), N01 = rect_slots(I, a, l, q, d);
+        const uint64_t N10 = rect_slots(I, l, b, cc, q);
+        const uint32_t quad = (ci >= l ? 2u : 0u) + (cj >= q ? 1u : 0u);
+        const uint64_t X00 = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, N00, k);
+        uint64_t X01 = 0, X10 = 0;
+        if (quad >= 1) X01 = hyp(make_stream(I.seed, code, 1, TAG_UTREE), Nn - N00, N01, k - X00);
+        if (quad >= 2) X10 = hyp(make_stream(I.seed, code, 2, TAG_UTREE), Nn - N00 - N01, N10, k - X00 - X01);
+        const uint64_t kk = quad == 0 ? X00 : quad == 1 ? X01 : quad == 2 ? X10 : k - X00 - X01 - X10;
+        if (quad < 2) b = l; else a = l;
+        if (quad & 1) cc = q; else d = q;
+        k = kk;
+        code = 4 * code + quad;
+    }
+}
+
+// Slots of tile range [lo, hi) of a chunk with Nc slots.
+__device__ __forceinline__ uint64_t tile_range_slots(uint64_t lo, uint64_t hi, uint32_t s, uint64_t Nc)
+{
+    const uint64_t e = hi << s;
+    return (e > Nc ? Nc : e) - (lo << s);
+}
+
+}  // namespace kg

@@ -1,0 +1,469 @@
+// kg_lib.hip -- host side of the C ABI declared in include/kg.h: argument
+// checks, the per-instance plan (chunk count, tile exponent), workspace
+// layout, and the launch sequence count -> scan -> plan -> sample.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/kg.h"
+#include "kg_kernels.hpp"
+
+namespace kg {
+__device__ double g_lnf_tab[kLnfTab + 1];
+}
+
+using namespace kg;
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+constexpr uint32_t kSpecVersion = 1;
+
+// Non-semantic knobs.
+int64_t g_leaf_cap = 0;        // 0: default
+int64_t g_sample_waves = 0;    // per CU
+int64_t g_plan_waves = 0;      // per CU
+int64_t g_time_kernels = 0;
+
+// Event pairs recorded around kernel launches while timing is on.
+std::mutex g_time_mu;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[4];
+
+struct KernelTimer {
+    int id;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer(int kid, hipStream_t st) : id(kid), s(st)
+    {
+        if (!g_time_kernels) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, s);
+    }
+    ~KernelTimer()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        g_events[id].emplace_back(a, b);
+    }
+};
+
+constexpr int64_t kDefaultSampleWaves = 16;
+constexpr int64_t kDefaultPlanWaves = 16;
+
+std::mutex g_init_mu;
+bool g_init_done[64];
+int g_num_cu[64];
+
+kg_status ensure_init(int *dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KG_EDEVICE;
+    *dev_out = dev;
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (g_init_done[dev]) return KG_OK;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return KG_EDEVICE;
+    g_num_cu[dev] = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    hipLaunchKernelGGL(lnf_init_kernel, dim3(1), dim3(64), 0, 0);
+    if (hipGetLastError() != hipSuccess) return KG_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return KG_EDEVICE;
+    g_init_done[dev] = true;
+    return KG_OK;
+}
+
+// Validation and the per-instance plan.
+kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
+{
+    if (in.flags != 0 || in.model > 1 || in.directed > 1) return KG_EINVAL;
+    if (in.n < 1 || in.chunks < 1 || (uint64_t)in.chunks > in.n) return KG_EINVAL;
+    if (in.n > (1ull << 32)) return KG_ERANGE;
+    const u128 N128 = in.directed ? (u128)in.n * (in.n - 1) : (u128)in.n * (in.n - 1) / 2;
+    if (N128 >= ((u128)1 << 53)) return KG_ERANGE;
+    if (in.directed ? (in.chunks > (1u << 31)) : (in.chunks > (1u << 15))) return KG_ERANGE;
+    const uint64_t N = (uint64_t)N128;
+    if (in.model == KG_GNM && in.m > N) return KG_EINVAL;
+    if (in.model == KG_GNP && !(in.p >= 0.0 && in.p <= 1.0)) return KG_EINVAL;
+    // tile exponent: smallest s in [9, 32] with 2^s m >= lambda N (G(n,m)) or
+    // 2^s p >= lambda (G(n,p))
+    uint32_t s = 32;
+    for (uint32_t t = 9; t <= 32; ++t) {
+        const bool ok = in.model == KG_GNM ? (((u128)in.m << t) >= (u128)kLambda * N)
+                                            : (ldexp(in.p, (int)t) >= (double)kLambda);
+        if (ok) { s = t; break; }
+    }
+    memset(&out, 0, sizeof(out));
+    out.n = in.n;
+    out.m = in.model == KG_GNM ? in.m : 0;
+    out.p = in.model == KG_GNP ? in.p : 0.0;
+    out.seed = in.seed;
+    out.model = in.model;
+    out.directed = in.directed;
+    out.P = in.chunks;
+    out.s = s;
+    out.nchunks = in.directed ? (uint64_t)in.chunks : (uint64_t)in.chunks * (in.chunks + 1) / 2;
+    // sum over chunks of ceil(N_c / 2^s) <= N / 2^s + chunks
+    tile_bound = (N >> s) + out.nchunks;
+    return KG_OK;
+}
+
+struct Layout {
+    uint64_t status, insts, off, tstart, ustart, tile_off, total;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+Layout layout_for(uint32_t ninst, uint64_t G, uint64_t Tb)
+{
+    Layout L;
+    uint64_t o = 0;
+    L.status = o; o = align256(o + 8 * sizeof(uint64_t));
+    L.insts = o; o = align256(o + (ninst > 1 ? ninst * sizeof(Inst) : 0));
+    L.off = o; o = align256(o + (G + 1) * 8);
+    L.tstart = o; o = align256(o + (G + 1) * 8);
+    L.ustart = o; o = align256(o + (G + 1) * 8);
+    L.tile_off = o; o = align256(o + (Tb + 1) * 8);
+    L.total = o;
+    return L;
+}
+
+struct Prepared {
+    std::vector<Inst> insts;
+    uint64_t G = 0, Tb = 0;
+    Layout L;
+};
+
+kg_status prepare(const kg_instance *in, uint32_t count, Prepared &P)
+{
+    if (!in || count == 0) return KG_EINVAL;
+    P.insts.resize(count);
+    P.G = 0;
+    P.Tb = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        uint64_t tb = 0;
+        const kg_status st = plan_instance(in[i], P.insts[i], tb);
+        if (st) return st;
+        P.insts[i].chunk_base = P.G;
+        P.G += P.insts[i].nchunks;
+        P.Tb += tb;
+    }
+    P.L = layout_for(count, P.G, P.Tb);
+    return KG_OK;
+}
+
+int64_t opt_or(int64_t v, int64_t dflt) { return v > 0 ? v : dflt; }
+
+struct Workspace {
+    char *base = nullptr;
+    bool owned = false;
+};
+
+kg_status acquire(Workspace &ws, void *d_ws, uint64_t ws_bytes, uint64_t need, hipStream_t s)
+{
+    if (d_ws) {
+        if (ws_bytes < need) return KG_ENOSPC;
+        ws.base = (char *)d_ws;
+        ws.owned = false;
+        return KG_OK;
+    }
+    void *p = nullptr;
+    if (hipMallocAsync(&p, need, s) != hipSuccess) return KG_EDEVICE;
+    ws.base = (char *)p;
+    ws.owned = true;
+    return KG_OK;
+}
+
+void release(Workspace &ws, hipStream_t s)
+{
+    if (ws.owned && ws.base) (void)hipFreeAsync(ws.base, s);
+    ws.base = nullptr;
+}
+
+Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t capacity)
+{
+    Job job;
+    memset(&job, 0, sizeof(job));
+    job.ninst = (uint32_t)P.insts.size();
+    int64_t cap = opt_or(g_leaf_cap, kCapMax);
+    if (cap > kCapMax) cap = kCapMax;
+    if (cap < 128) cap = 128;
+    job.leaf_cap = (uint32_t)cap;
+    job.G = P.G;
+    job.capacity = capacity;
+    job.tile_cap = P.Tb;
+    job.insts = job.ninst > 1 ? (const Inst *)(ws.base + P.L.insts) : nullptr;
+    job.one = P.insts[0];
+    job.off = (uint64_t *)(ws.base + P.L.off);
+    job.tstart = (uint64_t *)(ws.base + P.L.tstart);
+    job.ustart = (uint64_t *)(ws.base + P.L.ustart);
+    job.tile_off = (uint64_t *)(ws.base + P.L.tile_off);
+    job.status = (uint64_t *)(ws.base + P.L.status);
+    job.edges = edges;
+    return job;
+}
+
+// count + scan (+ instance offsets).
+kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s)
+{
+    if (job.ninst > 1) {
+        if (hipMemcpyAsync((void *)job.insts, P.insts.data(), P.insts.size() * sizeof(Inst),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return KG_EDEVICE;
+    }
+    const uint64_t nb = (P.G + 63) / 64;
+    {
+        KernelTimer tm(KG_KERNEL_COUNT, s);
+        hipLaunchKernelGGL(count_kernel, dim3((uint32_t)nb), dim3(64), 0, s, job);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SCAN, s);
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, job);
+    }
+    if (job.inst_off)
+        hipLaunchKernelGGL(inst_offsets_kernel, dim3((job.ninst + 1 + 255) / 256), dim3(256), 0, s, job);
+    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+}
+
+kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
+{
+    const int64_t cu = g_num_cu[dev];
+    const uint64_t ub = 2 * (P.Tb / kUnitTiles) + P.G + 1;   // bound on planner units
+    uint64_t pgrid = (uint64_t)(cu * opt_or(g_plan_waves, kDefaultPlanWaves));
+    if (pgrid > ub) pgrid = ub;
+    {
+        KernelTimer tm(KG_KERNEL_PLAN, s);
+        hipLaunchKernelGGL(plan_kernel, dim3((uint32_t)pgrid), dim3(64), 0, s, job);
+    }
+    uint64_t sgrid = (uint64_t)(cu * opt_or(g_sample_waves, kDefaultSampleWaves));
+    if (sgrid > P.Tb + 1) sgrid = P.Tb + 1;
+    {
+        KernelTimer tm(KG_KERNEL_SAMPLE, s);
+        hipLaunchKernelGGL(sample_kernel<kCapMax>, dim3((uint32_t)sgrid), dim3(64), 0, s, job);
+    }
+    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+}
+
+kg_status run(const kg_instance *inst, uint32_t count, uint32_t *edges, uint64_t capacity,
+              uint64_t *d_total, uint64_t *d_inst_off, void *d_ws, uint64_t ws_bytes, void *stream,
+              bool counts_only, uint64_t *h_total, uint64_t *d_counts)
+{
+    Prepared P;
+    kg_status st = prepare(inst, count, P);
+    if (st) return st;
+    int dev = 0;
+    st = ensure_init(&dev);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws;
+    st = acquire(ws, d_ws, ws_bytes, P.L.total, s);
+    if (st) return st;
+    Job job = make_job(P, ws, edges, capacity);
+    job.out_total = d_total;
+    job.inst_off = d_inst_off;
+    if (d_counts) {
+        // counts only: run the count kernel and copy the per-chunk counts out
+        const uint64_t nb = (P.G + 63) / 64;
+        hipLaunchKernelGGL(count_kernel, dim3((uint32_t)nb), dim3(64), 0, s, job);
+        if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+        else if (hipMemcpyAsync(d_counts, job.off, P.G * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            st = KG_EDEVICE;
+        release(ws, s);
+        return st;
+    }
+    st = launch_counts(P, job, s);
+    if (!st && counts_only) {
+        uint64_t tot = 0;
+        if (hipMemcpyAsync(&tot, job.status, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = KG_EDEVICE;
+        else
+            *h_total = tot;
+    } else if (!st) {
+        st = launch_generate(P, job, dev, s);
+    }
+    release(ws, s);
+    return st;
+}
+
+kg_instance make_inst(uint64_t n, uint32_t model, int directed, uint64_t m, double p, uint64_t seed,
+                      uint32_t chunks)
+{
+    kg_instance I;
+    memset(&I, 0, sizeof(I));
+    I.n = n;
+    I.model = model;
+    I.directed = directed ? 1u : 0u;
+    I.m = m;
+    I.p = p;
+    I.seed = seed;
+    I.chunks = chunks;
+    return I;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t kg_spec_version(void) { return kSpecVersion; }
+
+const char *kg_strerror(kg_status st)
+{
+    switch (st) {
+    case KG_OK: return "ok";
+    case KG_EINVAL: return "invalid argument";
+    case KG_ERANGE: return "argument outside the supported range";
+    case KG_ENOSPC: return "output or workspace too small";
+    case KG_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+kg_status kg_workspace_bytes(const kg_instance *inst, uint32_t count, uint64_t *bytes)
+{
+    if (!bytes) return KG_EINVAL;
+    Prepared P;
+    const kg_status st = prepare(inst, count, P);
+    if (st) return st;
+    *bytes = P.L.total;
+    return KG_OK;
+}
+
+kg_status kg_gnm(uint64_t n, uint64_t m, int directed, uint64_t seed, uint32_t chunks, uint32_t *d_edges,
+                 uint64_t capacity_edges, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    const kg_instance I = make_inst(n, KG_GNM, directed, m, 0.0, seed, chunks);
+    if (!d_edges && m > 0) return KG_EINVAL;
+    if (((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    Prepared P;
+    kg_status st = prepare(&I, 1, P);
+    if (st) return st;
+    if (capacity_edges < m) return KG_ENOSPC;
+    return run(&I, 1, d_edges, capacity_edges, nullptr, nullptr, d_workspace, workspace_bytes, stream, false,
+               nullptr, nullptr);
+}
+
+kg_status kg_gnp(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks, uint32_t *d_edges,
+                 uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
+                 void *stream)
+{
+    const kg_instance I = make_inst(n, KG_GNP, directed, 0, p, seed, chunks);
+    if (((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    if (!d_edges) capacity_edges = 0;
+    return run(&I, 1, d_edges, capacity_edges, d_total, nullptr, d_workspace, workspace_bytes, stream, false,
+               nullptr, nullptr);
+}
+
+kg_status kg_gnp_count(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks, uint64_t *h_total,
+                       void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_total) return KG_EINVAL;
+    const kg_instance I = make_inst(n, KG_GNP, directed, 0, p, seed, chunks);
+    return run(&I, 1, nullptr, 0, nullptr, nullptr, d_workspace, workspace_bytes, stream, true, h_total,
+               nullptr);
+}
+
+kg_status kg_chunk_counts(const kg_instance *inst, uint64_t *d_counts, void *d_workspace,
+                          uint64_t workspace_bytes, void *stream)
+{
+    if (!inst || !d_counts) return KG_EINVAL;
+    return run(inst, 1, nullptr, 0, nullptr, nullptr, d_workspace, workspace_bytes, stream, false, nullptr,
+               d_counts);
+}
+
+kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena, uint64_t arena_edges,
+                   uint64_t *d_inst_offsets, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_inst || count == 0 || !d_inst_offsets) return KG_EINVAL;
+    if (((uintptr_t)d_arena & 7) != 0) return KG_EINVAL;
+    if (!d_arena) arena_edges = 0;
+    return run(h_inst, count, d_arena, arena_edges, nullptr, d_inst_offsets, d_workspace, workspace_bytes,
+               stream, false, nullptr, nullptr);
+}
+
+uint64_t kg_instance_seed(uint64_t base, uint32_t i)
+{
+    const U4 w = philox(0, i, 0, TAG_INST, (uint32_t)base, (uint32_t)(base >> 32));
+    return ((uint64_t)w.y << 32) | w.x;
+}
+
+kg_status kg_set_option(int option, int64_t value)
+{
+    if (value < 0) return KG_EINVAL;
+    switch (option) {
+    case KG_OPT_LEAF_CAP:
+        if (value != 0 && (value < 128 || value > kCapMax)) return KG_ERANGE;
+        g_leaf_cap = value;
+        return KG_OK;
+    case KG_OPT_SAMPLE_WAVES:
+        if (value > 32) return KG_ERANGE;
+        g_sample_waves = value;
+        return KG_OK;
+    case KG_OPT_PLAN_WAVES:
+        if (value > 64) return KG_ERANGE;
+        g_plan_waves = value;
+        return KG_OK;
+    case KG_OPT_TIME_KERNELS:
+        if (value > 1) return KG_ERANGE;
+        g_time_kernels = value;
+        return KG_OK;
+    default:
+        return KG_EINVAL;
+    }
+}
+
+kg_status kg_kernel_time_read(int kernel, double *ms_total, uint64_t *launches)
+{
+    if (kernel < 0 || kernel > 3 || !ms_total || !launches) return KG_EINVAL;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        ev.swap(g_events[kernel]);
+    }
+    double tot = 0.0;
+    kg_status st = KG_OK;
+    for (auto &e : ev) {
+        float ms = 0.f;
+        if (hipEventSynchronize(e.second) != hipSuccess || hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess)
+            st = KG_EDEVICE;
+        tot += ms;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    *ms_total = tot;
+    *launches = ev.size();
+    return st;
+}
+
+kg_status kg_eval(int fn, const void *d_in, void *d_out, uint64_t n, void *stream)
+{
+    if (fn < KG_EVAL_PHILOX || fn > KG_EVAL_SQRT_DIV) return KG_EINVAL;
+    if (n == 0) return KG_OK;
+    if (!d_in || !d_out) return KG_EINVAL;
+    int dev = 0;
+    const kg_status st = ensure_init(&dev);
+    if (st) return st;
+    const uint64_t nb = (n + 255) / 256;
+    if (nb > 0x7FFFFFFFull) return KG_ERANGE;
+    hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)nb), dim3(256), 0, (hipStream_t)stream, fn, d_in, d_out, n);
+    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+}
+
+int64_t kg_get_option(int option)
+{
+    switch (option) {
+    case KG_OPT_LEAF_CAP: return opt_or(g_leaf_cap, kCapMax);
+    case KG_OPT_SAMPLE_WAVES: return opt_or(g_sample_waves, kDefaultSampleWaves);
+    case KG_OPT_PLAN_WAVES: return opt_or(g_plan_waves, kDefaultPlanWaves);
+    case KG_OPT_TIME_KERNELS: return g_time_kernels;
+    default: return -1;
+    }
+}
+
+}  // extern "C"
