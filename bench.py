@@ -1,0 +1,209 @@
+"""Benchmark of the MI355X Erdos-Renyi generator (one GPU).
+
+Default workload: undirected G(n,m), n = 2^26 vertices, m = 2^31 edges from
+the strict upper triangle, P = 256 sections (a 256 x 256 chunk grid of 2^16
+cells, 32,896 triangle chunks), seeds 1..3 in turn, uint32 (u,v) output.
+One step = one kg_gnm call: chunk counts, offsets, tile plan and sampling of
+all 2^31 edges into a preallocated 16 GiB buffer resident in HBM.
+
+Prints ONE JSON line: edges/s (value), the sampler's achieved HBM write
+bandwidth against the 8 TB/s peak (roofline), and the CPU oracle timed on a
+bounded sample of the same workload on this host (cpu_baseline).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_EDGE = 8
+
+WORKLOADS = {
+    # name: (description, n, m, p, directed, P, model)
+    "gnm_undirected_n26_m31": ("undirected G(n,m) n=2^26 m=2^31 P=256 sections (32896 chunks)",
+                               2**26, 2**31, 0.0, False, 256, 0),
+    "gnm_directed_n16_m20": ("directed G(n,m) n=2^16 m=2^20 P=64 chunks", 2**16, 2**20, 0.0, True, 64, 0),
+    "gnp_directed_n25_d16": ("directed G(n,p) n=2^25 p=16/(n-1) P=2^16 chunks",
+                             2**25, 0, 16.0 / (2**25 - 1), True, 2**16, 1),
+    "gnp_undirected_n25_d64": ("undirected G(n,p) n=2^25 p=64/(n-1) P=256 sections",
+                               2**25, 0, 64.0 / (2**25 - 1), False, 256, 1),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kg_device.hpp", "kg_kernels.hpp", "kg_lib.hip"):
+        with open(os.path.join(ROOT, "paper_1710_07565_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload):
+    """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sample_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload)
+    if not ent or ent.get("kernel_source") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(desc, seconds):
+    """The oracle (plain C, OpenMP over chunks) on a bounded sample of the
+    same workload: whole chunks in canonical order, blocks of 256, until
+    `seconds` have passed; the count pass is charged pro rata."""
+    import numpy as np
+    from oracle import kgref
+    _, n, m, p, directed, P, model = desc
+    I = kgref.inst(n, m=m, p=p, directed=directed, seed=1, chunks=P, model=model)
+    threads = kgref.max_threads()
+    t0 = time.perf_counter()
+    counts = kgref.chunk_counts(I)
+    t_counts = time.perf_counter() - t0
+    C = len(counts)
+    buf = np.zeros((int(counts[:256].sum()) * 2 + 1024, 2), dtype=np.uint32)
+    edges = 0
+    done = 0
+    t_gen = 0.0
+    # spread the sampled blocks over the chunk grid
+    starts = list(range(0, C, 256))
+    order = starts[::7] + [s for i, s in enumerate(starts) if i % 7]
+    for c0 in order:
+        c1 = min(C, c0 + 256)
+        need = int(counts[c0:c1].sum())
+        if buf.shape[0] < need:
+            buf = np.zeros((need, 2), dtype=np.uint32)
+        t0 = time.perf_counter()
+        r = kgref.generate_chunks(I, counts, c0, c1, out=buf, threads=threads)
+        t_gen += time.perf_counter() - t0
+        edges += len(r)
+        done += c1 - c0
+        if t_gen >= seconds:
+            break
+    t = t_gen + t_counts * done / C
+    return {"value": edges / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d chunks (%d edges, %.1f s), seed 1" % (done, C, edges, t)}
+
+
+def run_plain(args, desc):
+    import torch
+    import paper_1710_07565_amd as kg
+    name, n, m, p, directed, P, model = (args.workload,) + desc[1:]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    seeds = [1, 2, 3]
+    if model == 0:
+        cap = m
+    else:
+        mean = p * (n * (n - 1) // (1 if directed else 2))
+        cap = int(mean + 12 * mean ** 0.5 + 1024)
+    inst = kg.Instance(n, model, directed, m, p, 1, P)
+    ws = torch.empty(kg.workspace_bytes([inst]), dtype=torch.uint8, device=dev)
+    out = torch.empty((cap, 2), dtype=torch.uint32, device=dev)
+    total = torch.zeros(1, dtype=torch.uint64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        seed = seeds[i % len(seeds)]
+        if model == 0:
+            kg.gnm(n, m, directed, seed, P, out=out, workspace=ws, stream=stream)
+        else:
+            kg.gnp(n, p, directed, seed, P, out=out, total=total, workspace=ws, stream=stream)
+
+    log("bench: %s, warmup %d, steps %d" % (desc[0], args.warmup, args.steps))
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    edges_per_step = []
+    for i in range(args.steps):
+        if model == 0:
+            edges_per_step.append(m)
+        else:
+            edges_per_step.append(kg.gnp_count(n, p, directed, seeds[i % len(seeds)], P, workspace=ws))
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
+    for k in range(4):
+        kg.kernel_time_read(k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
+    ms = e0.elapsed_time(e1)
+    kt = {nm: kg.kernel_time_read(k) for k, nm in enumerate(["count", "scan", "plan", "sample"])}
+    if model == 1:
+        got = int(total.view(torch.int64).item())
+        assert got == edges_per_step[(args.steps - 1) % len(edges_per_step)], "edge total mismatch"
+    E = sum(edges_per_step)
+    ms_per_step = ms / args.steps
+    samp_ms, samp_n = kt["sample"]
+    samp_avg = samp_ms / max(samp_n, 1)
+    bytes_per_launch = BYTES_PER_EDGE * E / args.steps
+    achieved = bytes_per_launch / (samp_avg * 1e-3) / 1e9
+    traffic = traffic_for(name)
+    res = {
+        "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
+        "value": E / (ms * 1e-3),
+        "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": desc[0], "n": n, "m": m, "p": p, "directed": directed, "P": P,
+                   "seeds": seeds, "edges_per_step": E // args.steps},
+        "pct_hbm_write_bw": 100.0 * BYTES_PER_EDGE * E / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "sample_kernel", "avg_launch_ms": samp_avg,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "wall_s_timed": wall,
+    }
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gnm_undirected_n26_m31", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the generator needs no communication and this build "
+              "measures a single MI355X (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    desc = WORKLOADS[args.workload]
+    res = run_plain(args, desc)
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host (%.0f s budget)" % args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(desc, args.cpu_seconds)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

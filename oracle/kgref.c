@@ -953,3 +953,32 @@ void kgref_eval_many(int fn, const void *in, void *out, uint64_t n)
         }
     }
 }
+
+/* Edges of the chunks [c0, c1), concatenated in canonical order, given all
+ * chunk counts; chunks in parallel.  Returns the number of edges written or a
+ * negative status (KGREF_ENOSPC if they exceed cap). */
+int64_t kgref_generate_chunks(const kgref_inst *I, const uint64_t *counts, uint64_t c0, uint64_t c1,
+                              uint32_t *out, uint64_t cap, int threads)
+{
+    int st = kgref_validate(I);
+    if (st) return st;
+    uint64_t C = kgref_num_chunks(I);
+    if (c0 > c1 || c1 > C) return KGREF_EINVAL;
+    uint64_t *off = (uint64_t *)malloc((c1 - c0 + 1) * sizeof(uint64_t));
+    off[0] = 0;
+    for (uint64_t c = c0; c < c1; c++) off[c - c0 + 1] = off[c - c0] + counts[c];
+    uint64_t total = off[c1 - c0];
+    if (total > cap) { free(off); return KGREF_ENOSPC; }
+    int err = 0;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+#endif
+    for (int64_t c = (int64_t)c0; c < (int64_t)c1; c++) {
+        int64_t r = kgref_chunk_edges_given(I, (uint64_t)c, counts[c], out + 2 * off[c - c0]);
+        if (r < 0 || (uint64_t)r != counts[c]) err |= 1;
+    }
+    (void)threads;
+    free(off);
+    return err ? KGREF_EINVAL : (int64_t)total;
+}

@@ -70,6 +70,8 @@ def lib():
         L.kgref_instance_seed.argtypes = [u64, u32]; L.kgref_instance_seed.restype = u64
         L.kgref_max_threads.argtypes = []; L.kgref_max_threads.restype = ctypes.c_int
         L.kgref_eval_many.argtypes = [ctypes.c_int, vp, vp, u64]; L.kgref_eval_many.restype = None
+        L.kgref_generate_chunks.argtypes = [ip, vp, u64, u64, vp, u64, ctypes.c_int]
+        L.kgref_generate_chunks.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -202,3 +204,16 @@ def eval_many(fn, records, out_dtype, out_width):
     out = np.zeros((n, out_width), dtype=out_dtype)
     lib().kgref_eval_many(int(fn), _ptr(records), _ptr(out), n)
     return out
+
+
+def generate_chunks(I, counts, c0, c1, out=None, threads=0):
+    """Edges of chunks [c0, c1) given all chunk counts (canonical order)."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    need = int(counts[c0:c1].sum())
+    if out is None or out.shape[0] < need:
+        out = np.zeros((max(need, 1), 2), dtype=np.uint32)
+    r = lib().kgref_generate_chunks(ctypes.byref(I), _ptr(counts), int(c0), int(c1), _ptr(out), out.shape[0],
+                                    int(threads))
+    if r < 0:
+        raise ValueError("kgref_generate_chunks status %d" % r)
+    return out[:r]
