@@ -328,6 +328,17 @@ struct TileCtx {
     Decoder dec;
 };
 
+// wave-uniform values, kept in scalar registers
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x)
+{
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+__device__ __forceinline__ double unid(double x)
+{
+    return __longlong_as_double((long long)uni64((uint64_t)__double_as_longlong(x)));
+}
+
 __device__ __forceinline__ void store_edge(uint32_t *edges, uint64_t idx, uint2 e)
 {
     *reinterpret_cast<uint2 *>(edges + 2 * idx) = e;
@@ -584,14 +595,16 @@ __global__ __launch_bounds__(64) void sample_kernel(Job job)
         const uint32_t s = I.s;
         const uint64_t lstart = tl << s;
         TileCtx tc;
-        tc.S = (ch.N - lstart) < (1ull << s) ? (ch.N - lstart) : (1ull << s);
-        tc.bits = tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1);
-        tc.mask = tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1);
-        tc.full = tc.S == (1ull << tc.bits);
-        tc.st = make_stream(I.seed, (uint32_t)c, (uint32_t)tl, TAG_TLEAF);
-        tc.o0 = o0;
+        tc.S = uni64((ch.N - lstart) < (1ull << s) ? (ch.N - lstart) : (1ull << s));
+        tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
+        tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
+        tc.full = uni(tc.S == (1ull << tc.bits));
+        tc.st = Stream{uni((uint32_t)I.seed), uni((uint32_t)(I.seed >> 32)), uni((uint32_t)c), uni((uint32_t)tl),
+                       TAG_TLEAF};
+        tc.o0 = uni64(o0);
         tc.edges = job.edges;
         Decoder &dd = tc.dec;
+        dd.type = 0; dd.dv = 1; dd.rcp = 1.0; dd.u0 = dd.w0 = dd.a = dd.b = dd.c0 = dd.h = dd.Ttri = dd.lbase = 0;
         if (I.directed) {
             dd.type = 0;
             dd.dv = I.n - 1;
@@ -614,6 +627,11 @@ __global__ __launch_bounds__(64) void sample_kernel(Job job)
             dd.Ttri = ch.N;
             dd.lbase = lstart;
         }
+        dd.type = uni(dd.type);
+        dd.dv = uni64(dd.dv); dd.rcp = unid(dd.rcp);
+        dd.u0 = uni64(dd.u0); dd.w0 = uni64(dd.w0);
+        dd.a = uni64(dd.a); dd.b = uni64(dd.b); dd.c0 = uni64(dd.c0);
+        dd.h = uni64(dd.h); dd.Ttri = uni64(dd.Ttri); dd.lbase = uni64(dd.lbase);
         leaf_sample<CAP>(tc, s_bkt, s_hist, k, job.leaf_cap < CAP ? job.leaf_cap : CAP);
         __syncthreads();
     }
