@@ -150,7 +150,7 @@ def run_plain(args, desc):
     wall = time.perf_counter() - t0
     kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
     ms = e0.elapsed_time(e1)
-    kt = {nm: kg.kernel_time_read(k) for k, nm in enumerate(["count", "scan", "plan", "sample"])}
+    kt = {nm: kg.kernel_time_read(k) for k, nm in ((0, "count"), (1, "scan"), (2, "plan"), (3, "sample"))}
     if model == 1:
         got = int(total.view(torch.int64).item())
         assert got == edges_per_step[(args.steps - 1) % len(edges_per_step)], "edge total mismatch"
@@ -182,6 +182,146 @@ def run_plain(args, desc):
     return res
 
 
+def batch_totals(kg, insts, dev):
+    """Edges of every instance, from one kg_batch call with an empty arena
+    (counts and offsets only; nothing is written)."""
+    import torch
+    ws = torch.empty(kg.workspace_bytes(insts), dtype=torch.uint8, device=dev)
+    offs = torch.empty(len(insts) + 1, dtype=torch.uint64, device=dev)
+    empty = torch.empty((0, 2), dtype=torch.uint32, device=dev)
+    kg.batch(insts, arena=empty, offsets=offs, workspace=ws)
+    o = offs.view(torch.int64).cpu().numpy()
+    return [int(o[i + 1] - o[i]) for i in range(len(insts))]
+
+
+def run_batch(args):
+    """4096 uneven instances (n log-uniform in [2^10, 2^22], mean degree
+    uniform in [2, 64], half directed, half G(n,m)), per-instance seeds from
+    the base seed, generated by kg_batch in waves that fit the arena."""
+    import torch
+    import paper_1710_07565_amd as kg
+    from paper_1710_07565_amd import workloads
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    specs = workloads.batch_instances(args.instances, base_seed=1, seed_fn=kg.instance_seed)
+    insts = [kg.Instance(s.n, s.model, s.directed, s.m, s.p, s.seed, s.chunks) for s in specs]
+    tot = batch_totals(kg, insts, dev)
+    arena_edges = int(args.arena_gib * 2**30) // 8
+    waves, cur, acc = [], [], 0
+    for i, e in enumerate(tot):
+        if cur and acc + e > arena_edges:
+            waves.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += e
+    if cur:
+        waves.append(cur)
+    E = sum(tot)
+    log("bench: batch of %d instances, %d edges (%.1f GB), %d waves of <= %.0f GiB"
+        % (len(insts), E, 8 * E / 1e9, len(waves), args.arena_gib))
+    arena = torch.empty((min(arena_edges, max(sum(tot[i] for i in w) for w in waves)), 2), dtype=torch.uint32,
+                        device=dev)
+    wsmax = max(kg.workspace_bytes([insts[i] for i in w]) for w in waves)
+    ws = torch.empty(wsmax, dtype=torch.uint8, device=dev)
+    offs = torch.empty(len(insts) + 1, dtype=torch.uint64, device=dev)
+
+    def one_pass():
+        for w in waves:
+            kg.batch([insts[i] for i in w], arena=arena, offsets=offs, workspace=ws)
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
+    kg.kernel_time_read(3)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        one_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
+    ms = e0.elapsed_time(e1)
+    samp_ms, samp_n = kg.kernel_time_read(3)
+    # the same instances one call at a time (a sample, for the batching gain)
+    sample = list(range(0, len(insts), max(1, len(insts) // 256)))
+    one = torch.empty((max(tot[i] for i in sample), 2), dtype=torch.uint32, device=dev)
+    tot1 = torch.zeros(1, dtype=torch.uint64, device=dev)
+    ws1 = torch.empty(max(kg.workspace_bytes([insts[i]]) for i in sample), dtype=torch.uint8, device=dev)
+
+    def singles():
+        for i in sample:
+            I = insts[i]
+            if I.model == kg.GNM:
+                kg.gnm(I.n, I.m, I.directed, I.seed, I.chunks, out=one, workspace=ws1)
+            else:
+                kg.gnp(I.n, I.p, I.directed, I.seed, I.chunks, out=one, total=tot1, workspace=ws1)
+    singles()
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    singles()
+    f1.record()
+    torch.cuda.synchronize()
+    ms_single = f0.elapsed_time(f1)
+    E_sample = sum(tot[i] for i in sample)
+    w_sample = [insts[i] for i in sample]
+    kg.batch(w_sample, arena=arena, offsets=offs, workspace=ws)
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    kg.batch(w_sample, arena=arena, offsets=offs, workspace=ws)
+    g1.record()
+    torch.cuda.synchronize()
+    ms_batch_sample = g0.elapsed_time(g1)
+    value = E * args.steps / (ms * 1e-3)
+    return {
+        "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
+        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched: %d G(n,m)/G(n,p) instances, n log-uniform [2^10,2^22], mean degree "
+                               "uniform [2,64], half directed" % len(insts),
+                   "instances": len(insts), "edges_per_step": E, "waves": len(waves), "arena_gib": args.arena_gib},
+        "pct_hbm_write_bw": 100.0 * BYTES_PER_EDGE * value / (HBM_PEAK_GBS * 1e9),
+        "roofline": {"bound": "hbm", "achieved": BYTES_PER_EDGE * E * args.steps / (samp_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": BYTES_PER_EDGE * E * args.steps / (samp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "sample_kernel", "avg_launch_ms": samp_ms / max(samp_n, 1)},
+        "batching": {"sample_instances": len(sample), "sample_edges": E_sample,
+                     "one_call_each_edges_per_s": E_sample / (ms_single * 1e-3),
+                     "one_kg_batch_edges_per_s": E_sample / (ms_batch_sample * 1e-3)},
+    }
+
+
+def run_serve(args):
+    """Open-loop Poisson requests, continuous batching under an HBM budget."""
+    import torch
+    import paper_1710_07565_amd as kg
+    from paper_1710_07565_amd import serve, workloads
+    torch.cuda.set_device(0)
+    stream = workloads.request_stream(rate_per_s=args.rate, duration_s=args.duration, base_seed=1,
+                                      seed_fn=kg.instance_seed)
+    log("bench: serving %d requests over %.0f s at %.0f req/s" % (len(stream), args.duration, args.rate))
+    srv = serve.Server(budget_bytes=int(args.budget_gb * 1e9), streams=args.streams, max_batch=args.max_batch)
+    # warm up the library and allocator
+    w = workloads.request_stream(rate_per_s=200.0, duration_s=0.5, base_seed=99, seed_fn=kg.instance_seed)
+    serve.run_stream(srv, w, warmup_s=0.0)
+    reqs, st = serve.run_stream(srv, stream, warmup_s=args.serve_warmup,
+                                progress=lambda t, i, q, f: log("  t=%.0fs arrived=%d queued=%d inflight=%d"
+                                                                % (t, i, q, f)))
+    return {
+        "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
+        "value": st["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": st["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "served: Poisson %.0f req/s for %.0f s, G(n,m)/G(n,p) equal mix, n log-uniform "
+                               "[2^12,2^24], mean degree uniform [4,32], %.0f GB budget"
+                               % (args.rate, args.duration, args.budget_gb)},
+        "served": st,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,11 +330,38 @@ def main():
     ap.add_argument("--workload", default="gnm_undirected_n26_m31", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--instances", type=int, default=4096)
+    ap.add_argument("--arena-gib", type=float, default=96.0)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=256)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="first copy this many GiB device-to-device (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the generator needs no communication and this build "
               "measures a single MI355X (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy_gib > 0:
+        import torch
+        nb = int(args.calibrate_copy_gib * 2**30) // 4
+        src = torch.ones(nb, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of %d bytes (read %d + write %d)" % (4 * nb, 4 * nb, 4 * nb))
+        del src, dst
+    if args.mode == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.mode == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return
     desc = WORKLOADS[args.workload]
     res = run_plain(args, desc)
     if not args.no_cpu_baseline:

@@ -110,7 +110,8 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
 uint64_t kg_instance_seed(uint64_t base, uint32_t i);
 
 /* Non-semantic launch knobs (never change output bits).  A value of 0
- * restores the default.  Process-wide; set them before issuing calls. */
+ * restores the default (for the wave counts: as many workgroups as fit on a
+ * compute unit at once).  Process-wide; set them before issuing calls. */
 enum {
     KG_OPT_LEAF_CAP = 1,        /* samples a wave sorts in LDS per pass (128..1024) */
     KG_OPT_SAMPLE_WAVES = 2,    /* resident sampler waves per compute unit (1..32) */

@@ -4,7 +4,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkg.so")
+LIB_PATH = os.environ.get("KG_LIBRARY") or os.path.join(HERE, "libkg.so")
 
 KG_OK, KG_EINVAL, KG_ERANGE, KG_ENOSPC, KG_EDEVICE = 0, -1, -2, -3, -4
 KG_GNM, KG_GNP = 0, 1

@@ -22,7 +22,7 @@ namespace kg {
 // Constants of the method
 // ---------------------------------------------------------------------------
 constexpr uint32_t kLambda = 512;       // expected samples per tile (sampling threshold)
-constexpr uint32_t kUnitTiles = 256;    // tiles a planner wave expands at once
+constexpr uint32_t kUnitTiles = 64;     // most tiles of one planner unit (one lane expands it)
 constexpr uint32_t kLnfTab = 1024;      // ln k! tabulated for k <= kLnfTab
 
 enum : uint32_t { TAG_DTREE = 1, TAG_UTREE = 2, TAG_CBIN = 3, TAG_TTREE = 4, TAG_TLEAF = 5, TAG_INST = 6 };
@@ -120,7 +120,7 @@ __device__ __forceinline__ double atanh_series(double z)
     return z * r;
 }
 
-__device__ __noinline__ double log_f64(double x)
+__device__ __forceinline__ double log_f64(double x)
 {
     const double kLn2Hi = 0x1.62e42fee00000p-1;
     const double kLn2Lo = 0x1.a39ef35793c76p-33;
@@ -140,7 +140,7 @@ __device__ __noinline__ double log_f64(double x)
     return dk * kLn2Hi - ((hfsq - (s * (hfsq + R) + dk * kLn2Lo)) - u);
 }
 
-__device__ __noinline__ double log1p_f64(double x)
+__device__ __forceinline__ double log1p_f64(double x)
 {
     if (x > -0.25 && x < 0.25) {
         const double s = x / (2.0 + x);
@@ -170,7 +170,7 @@ __device__ __forceinline__ double stirling_corr(double z)
     return r * (1.0 / 12.0 - r2 * (1.0 / 360.0 - r2 * (1.0 / 1260.0)));
 }
 
-__device__ __noinline__ double stirling_diff(uint64_t a, uint64_t d)
+__device__ __forceinline__ double stirling_diff(uint64_t a, uint64_t d)
 {
     const double z = (double)(a + 1);
     const double zd = (double)(a + d + 1);
@@ -182,7 +182,7 @@ __device__ __noinline__ double stirling_diff(uint64_t a, uint64_t d)
 }
 
 // lnf(y) - lnf(x).
-__device__ __noinline__ double lnf_diff(uint64_t x, uint64_t y)
+__device__ __forceinline__ double lnf_diff(uint64_t x, uint64_t y)
 {
     if (x == y) return 0.0;
     double sign = 1.0;
@@ -264,7 +264,7 @@ __device__ __forceinline__ uint64_t rou_sample(const Stream &s, double a, double
 
 // Hypergeometric: how many of k draws without replacement from N items land
 // among K marked ones (the sample size of a sub-universe, Sec. 2.2).
-__device__ __noinline__ uint64_t hyp(const Stream &s, uint64_t N, uint64_t K, uint64_t k)
+__device__ __forceinline__ uint64_t hyp(const Stream &s, uint64_t N, uint64_t K, uint64_t k)
 {
     // symmetries: complement the draws, complement the marked set, swap roles
     uint64_t k1 = k, K1 = K;
@@ -298,9 +298,82 @@ __device__ __noinline__ uint64_t hyp(const Stream &s, uint64_t N, uint64_t K, ui
     return x;
 }
 
+// The same hypergeometric variate as hyp(), consumed one ratio-of-uniforms
+// proposal per step() so that lanes of a wave working on different variates
+// do not wait for each other's rejection loops.  Identical draws and result.
+struct HypRun {
+    Stream s;
+    uint64_t N, K, k1, hi, lo, M, x;
+    double a, h, upper_excl;
+    uint32_t j;
+    bool c1, c2, done;
+
+    __device__ __forceinline__ void init(const Stream &st, uint64_t N_, uint64_t K_, uint64_t k)
+    {
+        s = st;
+        N = N_;
+        K = K_;
+        k1 = k;
+        uint64_t K1 = K_;
+        c1 = c2 = false;
+        if (k1 > N - k1) { k1 = N - k1; c1 = true; }
+        if (K1 > N - K1) { K1 = N - K1; c2 = true; }
+        lo = k1 < K1 ? k1 : K1;
+        hi = k1 < K1 ? K1 : k1;
+        j = 0;
+        done = true;
+        if (lo == 0) {
+            x = 0;
+        } else if (lo <= 16) {
+            Draws64 d(s);
+            x = 0;
+            for (uint64_t i = 0; i < lo; ++i)
+                if (draw_below(d, N - i) < hi - x) ++x;
+        } else {
+            const double Nd = (double)N, Kd = (double)hi, kd = (double)lo;
+            const double pp = Kd / Nd;
+            const double mu = kd * pp;
+            const double var = (((Nd - kd) * kd) * pp) * (1.0 - pp) / (Nd - 1.0);
+            const double c = sqrt(var + 0.5);
+            h = kRouD1 * c + kRouD2;
+            a = mu + 0.5;
+            M = muldiv_floor(lo + 1, hi + 1, N + 2);
+            upper_excl = (double)lo + 1.0;
+            done = false;
+        }
+    }
+
+    // one proposal; true once the variate is known
+    __device__ __forceinline__ bool step()
+    {
+        if (done) return true;
+        const U4 w = s.block(j++);
+        const double U = unit_of(((uint64_t)w.y << 32) | w.x);
+        const double V = unit_of(((uint64_t)w.w << 32) | w.z);
+        const double t = a + h * (V - 0.5) / U;
+        if (!(t >= 0.0) || t >= upper_excl) return false;
+        const uint64_t X = (uint64_t)floor(t);
+        const double T = HypRatio{N, hi, lo, M}(X);
+        bool acc = false;
+        if (U * (4.0 - U) - 3.0 <= T) acc = true;
+        else if (U * (U - T) >= 1.0) acc = false;
+        else acc = 2.0 * log_f64(U) <= T;
+        if (acc) { x = X; done = true; }
+        return done;
+    }
+
+    __device__ __forceinline__ uint64_t result() const
+    {
+        uint64_t r = x;
+        if (c2) r = k1 - r;
+        if (c1) r = K - r;
+        return r;
+    }
+};
+
 // Binomial(N, p): a G(n,p) chunk's edge count (Sec. 4.3).  Small means by
 // geometric waiting times floor(log U / log(1-p)); otherwise ratio of uniforms.
-__device__ __noinline__ uint64_t bin_core(const Stream &s, uint64_t N, double p)
+__device__ __forceinline__ uint64_t bin_core(const Stream &s, uint64_t N, double p)
 {
     const double Nd = (double)N;
     if (Nd * p < 16.0) {
@@ -395,10 +468,10 @@ __device__ __forceinline__ uint64_t tiles_of(uint64_t N, uint32_t s)
     return (N + ((1ull << s) - 1)) >> s;
 }
 
-__device__ __forceinline__ uint32_t unit_depth(uint64_t T)
+__device__ __forceinline__ uint32_t unit_depth(uint64_t T, uint32_t ulog)
 {
     uint32_t d = 0;
-    while (((T + (1ull << d) - 1) >> d) > kUnitTiles) ++d;
+    while (((T + (1ull << d) - 1) >> d) > (1ull << ulog)) ++d;
     return d;
 }
 

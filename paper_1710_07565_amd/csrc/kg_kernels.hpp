@@ -16,6 +16,7 @@ namespace kg {
 struct Job {
     uint32_t ninst;
     uint32_t leaf_cap;       // samples sorted per LDS pass, <= kCapMax
+    uint32_t unit_log;       // planner units hold <= 2^unit_log tiles (launch shape only)
     uint64_t G;              // chunks over all instances
     uint64_t capacity;       // output room in edges
     uint64_t tile_cap;       // tile_off has tile_cap + 1 entries
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(64) void count_kernel(Job job)
     const uint64_t T = tiles_of(ch.N, I.s);
     job.off[g] = cnt;
     job.tstart[g] = T;
-    job.ustart[g] = T ? (1ull << unit_depth(T)) : 0;
+    job.ustart[g] = T ? (1ull << unit_depth(T, job.unit_log)) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -156,98 +157,107 @@ __global__ __launch_bounds__(256) void inst_offsets_kernel(Job job)
 }
 
 // ---------------------------------------------------------------------------
-// plan: one wavefront per unit, a subtree of <= 256 tiles of one chunk's tile
-// tree.  Lane 0 walks from the tile-tree root to the unit's root (the
-// communication-free path); the wave then expands the subtree level by level.
+// plan: one lane per planner unit (a subtree of <= 64 tiles of one chunk's
+// tile tree, at depth d, index j).  The lane walks from the tile-tree root
+// to the unit (the communication-free path: the count of the unit and the
+// counts left of it), then traverses the unit depth first, left child first,
+// so leaves come in tile order and each tile's output offset is a running
+// sum.  Every split is one HypRun, advanced by one proposal per loop trip;
+// pending right children wait on a small per-lane stack in LDS.
 // ---------------------------------------------------------------------------
+constexpr int kPlanStack = 8;   // > depth of a unit subtree (6 for 64 tiles)
+
 __global__ __launch_bounds__(64) void plan_kernel(Job job)
 {
-    __shared__ uint32_t s_lo[2][kUnitTiles], s_hi[2][kUnitTiles], s_heap[2][kUnitTiles];
-    __shared__ uint64_t s_k[2][kUnitTiles];
-    __shared__ uint64_t s_tc[kUnitTiles];
-    __shared__ uint64_t s_root[4];
+    __shared__ uint64_t st_k[kPlanStack][64];
+    __shared__ uint32_t st_lo[kPlanStack][64], st_hi[kPlanStack][64], st_heap[kPlanStack][64];
     const uint32_t lane = threadIdx.x;
     if (job.status[1]) return;
     const uint64_t U = job.status[3];
-    const uint64_t G = job.G;
-    for (uint64_t u = blockIdx.x; u < U; u += gridDim.x) {
-        const uint64_t g = last_le(job.ustart, G, u);
+    const uint64_t TL = (uint64_t)gridDim.x * 64;
+    uint64_t u = (uint64_t)blockIdx.x * 64 + lane;
+    bool active = u < U;
+    // unit state
+    uint64_t seed = 0, Nc = 0, tbase = 0, obase = 0, run = 0, j = 0;
+    uint32_t c = 0, s = 0, d = 0, lev = 0;
+    // current node (tile range within the chunk, count, heap id); path mode
+    // while lev < d
+    uint64_t lo = 0, hi = 0, k = 0;
+    uint32_t heap = 1;
+    int sp = 0;
+    bool need_node = true, running = false;
+    HypRun hr;
+    hr.done = true;
+    if (active) {
+        const uint64_t g = last_le(job.ustart, job.G, u);
         const Inst &I = inst_at(job, inst_of_chunk(job, g));
-        const uint64_t c = g - I.chunk_base;
-        const Chunk ch = chunk_geometry(I, c);
-        const uint32_t s = I.s;
-        const uint64_t T = tiles_of(ch.N, s);
+        const uint64_t cc = g - I.chunk_base;
+        const Chunk ch = chunk_geometry(I, cc);
+        seed = I.seed; c = (uint32_t)cc; s = I.s; Nc = ch.N;
         const uint64_t units = job.ustart[g + 1] - job.ustart[g];
-        const uint32_t d = 63 - __clzll(units);
-        const uint64_t j = u - job.ustart[g];
-        if (lane == 0) {
-            uint64_t lo = 0, hi = T, k = job.off[g + 1] - job.off[g], base = 0;
-            uint32_t heap = 1;
-            for (uint32_t lev = 0; lev < d; ++lev) {
+        d = 63 - __clzll(units);
+        j = u - job.ustart[g];
+        tbase = job.tstart[g];
+        obase = job.off[g];
+        lo = 0; hi = tiles_of(Nc, s); k = job.off[g + 1] - obase; heap = 1; lev = 0; run = 0; sp = 0;
+        need_node = false;
+    }
+    while (__any(active)) {
+        if (active) {
+            if (need_node) {
+                if (sp > 0) {
+                    --sp;
+                    lo = st_lo[sp][lane]; hi = st_hi[sp][lane]; k = st_k[sp][lane]; heap = st_heap[sp][lane];
+                    need_node = false;
+                } else {
+                    u += TL;
+                    if (u >= U) {
+                        active = false;
+                    } else {
+                        const uint64_t g = last_le(job.ustart, job.G, u);
+                        const Inst &I = inst_at(job, inst_of_chunk(job, g));
+                        const uint64_t cc = g - I.chunk_base;
+                        const Chunk ch = chunk_geometry(I, cc);
+                        seed = I.seed; c = (uint32_t)cc; s = I.s; Nc = ch.N;
+                        const uint64_t units = job.ustart[g + 1] - job.ustart[g];
+                        d = 63 - __clzll(units);
+                        j = u - job.ustart[g];
+                        tbase = job.tstart[g];
+                        obase = job.off[g];
+                        lo = 0; hi = tiles_of(Nc, s); k = job.off[g + 1] - obase; heap = 1; lev = 0; run = 0;
+                        need_node = false;
+                    }
+                }
+            }
+            if (active && !need_node && !running) {
+                if (lev >= d && hi - lo == 1) {
+                    job.tile_off[tbase + lo] = obase + run;
+                    run += k;
+                    need_node = true;
+                } else {
+                    const uint64_t mid = lo + (hi - lo + 1) / 2;
+                    hr.init(make_stream(seed, c, heap, TAG_TTREE), tile_range_slots(lo, hi, s, Nc),
+                            tile_range_slots(lo, mid, s, Nc), k);
+                    running = true;
+                }
+            }
+            if (active && running && hr.step()) {
+                const uint64_t X = hr.result();
                 const uint64_t mid = lo + (hi - lo + 1) / 2;
-                const uint64_t X = hyp(make_stream(I.seed, (uint32_t)c, heap, TAG_TTREE),
-                                       tile_range_slots(lo, hi, s, ch.N), tile_range_slots(lo, mid, s, ch.N), k);
-                if (((j >> (d - 1 - lev)) & 1) == 0) { hi = mid; k = X; heap = 2 * heap; }
-                else { lo = mid; k = k - X; base += X; heap = 2 * heap + 1; }
-            }
-            s_root[0] = lo; s_root[1] = hi; s_root[2] = k; s_root[3] = base;
-            s_lo[0][0] = 0; s_hi[0][0] = (uint32_t)(hi - lo); s_k[0][0] = k; s_heap[0][0] = heap;
-        }
-        __syncthreads();
-        const uint64_t rlo = s_root[0], nt = s_root[1] - s_root[0], base = s_root[3];
-        uint32_t cur = 0, cnt = 1;
-        for (;;) {
-            int internal = 0;
-            for (uint32_t e = lane; e < cnt; e += 64) {
-                const uint32_t a = s_lo[cur][e], b = s_hi[cur][e];
-                const uint64_t kk = s_k[cur][e];
-                const uint32_t h = s_heap[cur][e];
-                uint32_t la = 0, lb = 0, ra = 0, rb = 0;
-                uint64_t lk = 0, rk = 0;
-                if (b - a == 1) {
-                    s_tc[a] = kk;
-                } else if (b - a > 1) {
-                    const uint32_t mid = a + (b - a + 1) / 2;
-                    const uint64_t X = hyp(make_stream(I.seed, (uint32_t)c, h, TAG_TTREE),
-                                           tile_range_slots(rlo + a, rlo + b, s, ch.N),
-                                           tile_range_slots(rlo + a, rlo + mid, s, ch.N), kk);
-                    la = a; lb = mid; lk = X; ra = mid; rb = b; rk = kk - X;
-                    internal = 1;
-                }
-                if (2 * e + 1 < kUnitTiles) {
-                    s_lo[cur ^ 1][2 * e] = la; s_hi[cur ^ 1][2 * e] = lb; s_k[cur ^ 1][2 * e] = lk;
-                    s_heap[cur ^ 1][2 * e] = 2 * h;
-                    s_lo[cur ^ 1][2 * e + 1] = ra; s_hi[cur ^ 1][2 * e + 1] = rb; s_k[cur ^ 1][2 * e + 1] = rk;
-                    s_heap[cur ^ 1][2 * e + 1] = 2 * h + 1;
+                running = false;
+                if (lev < d) {
+                    // on the path to the unit: follow bit (d-1-lev) of j
+                    if (((j >> (d - 1 - lev)) & 1) == 0) { hi = mid; k = X; heap = 2 * heap; }
+                    else { lo = mid; k = k - X; run += X; heap = 2 * heap + 1; }
+                    ++lev;
+                } else {
+                    st_lo[sp][lane] = (uint32_t)mid; st_hi[sp][lane] = (uint32_t)hi;
+                    st_k[sp][lane] = k - X; st_heap[sp][lane] = 2 * heap + 1;
+                    ++sp;
+                    hi = mid; k = X; heap = 2 * heap;
                 }
             }
-            if (!__syncthreads_or(internal)) break;
-            cur ^= 1;
-            cnt *= 2;
         }
-        // exclusive scan of the tile counts (4 per lane), then the offsets
-        uint64_t v[4], sum = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t tt = lane * 4 + q;
-            v[q] = tt < nt ? s_tc[tt] : 0;
-            sum += v[q];
-        }
-        uint64_t incl = sum;
-#pragma unroll
-        for (int dlt = 1; dlt < 64; dlt <<= 1) {
-            const uint64_t o = __shfl_up(incl, dlt, 64);
-            if (lane >= (uint32_t)dlt) incl += o;
-        }
-        uint64_t run = job.off[g] + base + (incl - sum);
-        const uint64_t t0 = job.tstart[g] + rlo;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t tt = lane * 4 + q;
-            if (tt < nt) job.tile_off[t0 + tt] = run;
-            run += v[q];
-        }
-        __syncthreads();
     }
 }
 
@@ -274,16 +284,38 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
 }
 
 // Slot -> edge of one tile (Sec. 4.1 and 4.2 offset computations).
+// Directed: slot w of row u (w in [0, n-1)) is column w + [w >= u].
+// Rectangle: local l -> (row a + l / width, column b + l % width).
+// Triangle: rows counted from the bottom hold 1, 2, 3, ... slots.
+// The divisions by n - 1 or by the section width use a binary64 reciprocal
+// estimate corrected by one step (exact for dividends below 2^33), or a shift
+// when the divisor is a power of two.
 struct Decoder {
     uint32_t type;      // 0 directed, 1 rectangle, 2 triangle
+    uint32_t pow2;      // divisor is 2^sh
+    uint32_t sh;
+    uint32_t small;     // every dividend of the tile fits 32 bits
     uint64_t dv;        // directed: n - 1; rectangle: section width
     double rcp;         // 1 / dv
-    uint64_t u0, w0;    // directed: row and column offset of the tile start
-    uint64_t a, b, c0;  // rectangle: first row, first column, column offset of the tile start
+    uint64_t u0, w0;    // directed: row / slot in row of the tile start
+    uint64_t a, b, c0;  // rectangle: row of the tile start, first column, column of the tile start
     uint64_t h, Ttri, lbase;  // triangle: section size, its slots, tile start
 
-    __device__ __forceinline__ uint64_t fdiv(uint64_t x, uint64_t &rem) const
+    __device__ __forceinline__ uint64_t divmod(uint64_t x, uint64_t &rem) const
     {
+        if (pow2) {
+            rem = x & (dv - 1);
+            return x >> sh;
+        }
+        if (small) {
+            const uint32_t x32 = (uint32_t)x, d32 = (uint32_t)dv;
+            uint32_t q = (uint32_t)((double)x32 * rcp);
+            int32_t r = (int32_t)(x32 - q * d32);
+            if (r < 0) { --q; r += (int32_t)d32; }
+            else if ((uint32_t)r >= d32) { ++q; r -= (int32_t)d32; }
+            rem = (uint32_t)r;
+            return q;
+        }
         uint64_t q = (uint64_t)((double)x * rcp);
         int64_t r = (int64_t)(x - q * dv);
         if (r < 0) { --q; r += (int64_t)dv; }
@@ -296,16 +328,15 @@ struct Decoder {
     {
         if (type == 0) {
             uint64_t r;
-            const uint64_t q = fdiv(w0 + x, r);
+            const uint64_t q = divmod(w0 + x, r);
             const uint64_t u = u0 + q;
             return make_uint2((uint32_t)u, (uint32_t)(r + (r >= u)));
         }
         if (type == 1) {
             uint64_t r;
-            const uint64_t q = fdiv(c0 + x, r);
+            const uint64_t q = divmod(c0 + x, r);
             return make_uint2((uint32_t)(a + q), (uint32_t)(b + r));
         }
-        // triangle: rows counted from the bottom hold 1, 2, 3, ... slots
         const uint64_t l = lbase + x;
         const uint64_t lr = Ttri - 1 - l;
         uint64_t q = (uint64_t)((sqrt(8.0 * (double)lr + 1.0) - 1.0) * 0.5);
@@ -504,6 +535,299 @@ __device__ uint32_t collect_sorted(const TileCtx &t, uint32_t *s, uint32_t *hist
     return kept;
 }
 
+// A lane's run of `per` consecutive counters starting at h0 (per is 1, 2, 4,
+// 8 or 16; runs of 4 or more are 16-byte aligned).
+__device__ __forceinline__ void load_run(const uint32_t *h, uint32_t h0, uint32_t per, uint32_t NB, uint32_t *v)
+{
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = 0;
+    if (h0 >= NB) return;
+    if (per >= 4) {
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+            if ((uint32_t)i < per) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(h + h0 + i);
+                v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) if ((uint32_t)i < per) v[i] = h[h0 + i];
+    }
+}
+
+__device__ __forceinline__ void store_run(uint32_t *h, uint32_t h0, uint32_t per, uint32_t NB, const uint32_t *v)
+{
+    if (h0 >= NB) return;
+    if (per >= 4) {
+#pragma unroll
+        for (int i = 0; i < 16; i += 4)
+            if ((uint32_t)i < per) *reinterpret_cast<uint4 *>(h + h0 + i) = make_uint4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) if ((uint32_t)i < per) h[h0 + i] = v[i];
+    }
+}
+
+// W consecutive LDS words starting at p0 (W = 4, 8 or 16; p0 a multiple of
+// W/2), loaded into / stored from registers, and a bitonic network that sorts
+// them ascending.
+template <int W>
+__device__ __forceinline__ void win_load(const uint32_t *s, uint32_t p0, uint32_t *v)
+{
+    if ((p0 & 3) == 0) {
+#pragma unroll
+        for (int i = 0; i < W; i += 4) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(s + p0 + i);
+            v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < W; i += 2) {
+            const uint2 q = *reinterpret_cast<const uint2 *>(s + p0 + i);
+            v[i] = q.x; v[i + 1] = q.y;
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void win_store(uint32_t *s, uint32_t p0, const uint32_t *v)
+{
+    if ((p0 & 3) == 0) {
+#pragma unroll
+        for (int i = 0; i < W; i += 4)
+            *reinterpret_cast<uint4 *>(s + p0 + i) = make_uint4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < W; i += 2) *reinterpret_cast<uint2 *>(s + p0 + i) = make_uint2(v[i], v[i + 1]);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void win_sort(uint32_t *v)
+{
+#pragma unroll
+    for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = v[i], b = v[l];
+                    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    if ((i & k) == 0) { v[i] = lo; v[l] = hi; } else { v[i] = hi; v[l] = lo; }
+                }
+            }
+        }
+    }
+}
+
+// Two window passes over s[0..V) with windows of 8 keys, R (1 or 2)
+// consecutive windows per lane (s padded with ~0 up to 512 R + 4): lane L
+// sorts windows [8 (R L + r), +8), then the windows shifted by 4.  The result
+// is sorted whenever no bucket of more than 5 keys straddles a window
+// boundary; order and repeats are checked from the registers of the second
+// pass (one shuffle for the boundary between lanes).  Returns
+// (bad ? 1 : 0) | (repeats << 1).
+__device__ __forceinline__ uint32_t window_passes(uint32_t *s, uint32_t V, uint32_t R)
+{
+    const uint32_t lane = threadIdx.x;
+    uint32_t v[8], head[4];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+        if (r < R) {
+            const uint32_t p0 = 8 * (R * lane + r);
+            win_load<8>(s, p0, v);
+            win_sort<8>(v);
+            win_store<8>(s, p0, v);
+            if (r == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) head[i] = v[i];
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t bad = 0, dup = 0, prev_last = 0, first = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+        if (r < R) {
+            const uint32_t p0 = 8 * (R * lane + r) + 4;
+            win_load<8>(s, p0, v);
+            win_sort<8>(v);
+            win_store<8>(s, p0, v);
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                if (p0 + i + 1 < V) { bad |= v[i] > v[i + 1]; dup += v[i] == v[i + 1]; }
+            if (r == 0) first = v[0];
+            else if (p0 < V) { bad |= prev_last > v[0]; dup += prev_last == v[0]; }
+            prev_last = v[7];
+        }
+    }
+    const uint32_t last_p = 8 * (R * lane + R - 1) + 4 + 7;     // position of prev_last
+    const uint32_t nxt = __shfl_down(first, 1, 64);
+    if (lane < 63 && last_p + 1 < V) { bad |= prev_last > nxt; dup += prev_last == nxt; }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t y = i + 1 < 4 ? head[i + 1] : first;
+            if ((uint32_t)i + 1 < V) { bad |= head[i] > y; dup += head[i] == y; }
+        }
+    }
+    return bad | (dup << 1);
+}
+
+// Write sorted keys s[0..n) as edges o0 .. o0+n-1: lane-strided, four keys
+// per lane per round so that their LDS reads overlap.
+__device__ __forceinline__ void emit_sorted(const TileCtx &t, const uint32_t *s, uint32_t n)
+{
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t b = 0; b < n; b += 256) {
+        uint32_t x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t p = b + lane + 64 * i;
+            x[i] = p < n ? s[p] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t p = b + lane + 64 * i;
+            if (p < n) store_edge(t.edges, t.o0 + p, t.dec(x[i]));
+        }
+    }
+}
+
+// Fast base case for tiles whose draws fit one LDS pass (J <= cap): lane L
+// keeps in registers the words of blocks L, L + 64, ... (draw d = 4 block + q),
+// so the histogram atomics run while the words are produced and nothing is
+// staged.  Counting sort on the top bits of the key with about two buckets
+// per key: exclusive scan, scatter, then every lane sorts the buckets it owns
+// (a contiguous range it knows from the scan) in place and counts repeats.
+// Leaves the sorted distinct set in s[0..ke) and returns true, or false when
+// J would exceed cap (the caller then uses key sub-ranges).
+template <int CAP>
+__device__ __forceinline__ bool leaf_fast(const TileCtx &t, uint32_t *s, uint32_t *hist, uint32_t ke, uint32_t cap)
+{
+    constexpr int R = CAP / 256;
+    const uint32_t lane = threadIdx.x;
+    uint32_t nbb = 33 - __clz(ke | 1);                  // ~2 buckets per key
+    const uint32_t nbmax = 31 - __clz((uint32_t)CAP);
+    if (nbb > nbmax) nbb = nbmax;
+    if (nbb > t.bits) nbb = t.bits;
+    const uint32_t NB = 1u << nbb;
+    const uint32_t shift = t.bits - nbb;
+    const uint32_t per = NB >= 64 ? NB / 64 : 1;        // buckets owned by a lane
+    const uint32_t h0 = lane * per;
+    uint32_t J = ke;
+    for (;;) {
+        if (J > cap) return false;
+        {
+            uint32_t z[16] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            store_run(hist, h0, per, NB, z);
+        }
+        {
+            // draws straight to LDS: s[d] = word d masked, or ~0 if rejected
+            const uint32_t nblk = (J + 3) >> 2;
+#pragma unroll 1
+            for (uint32_t blk = lane; blk < nblk; blk += 64) {
+                const U4 w = t.st.block(blk);
+                uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (!(4 * blk + q < J && (t.full || v[q] < t.S))) v[q] = 0xFFFFFFFFu;
+                *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
+            }
+            __syncthreads();
+            uint32_t xs[4 * R], sl[4 * R];
+            const bool allv = t.full;   // with S = 2^bits no draw is rejected
+#pragma unroll
+            for (int e = 0; e < 4 * R; ++e) {
+                const uint32_t d = lane + 64u * e;
+                xs[e] = 0;
+                sl[e] = 0xFFFFFFFFu;
+                if (d < J) {
+                    const uint32_t x = s[d];
+                    if (allv || x != 0xFFFFFFFFu) {
+                        xs[e] = x;
+                        sl[e] = atomicAdd(&hist[x >> shift], 1u);
+                    }
+                }
+            }
+            __syncthreads();
+            // exclusive scan of hist[0..NB): lane owns per = NB/64 consecutive
+            // buckets, read and written with 16-byte LDS accesses
+            {
+                uint32_t cv[16];
+                load_run(hist, h0, per, NB, cv);
+                uint32_t sum = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) if ((uint32_t)i < per) sum += cv[i];
+                uint32_t incl = sum;
+#pragma unroll
+                for (int dlt = 1; dlt < 64; dlt <<= 1) {
+                    const uint32_t o = __shfl_up(incl, dlt, 64);
+                    if (lane >= (uint32_t)dlt) incl += o;
+                }
+                uint32_t run = incl - sum;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if ((uint32_t)i < per) { const uint32_t c = cv[i]; cv[i] = run; run += c; }
+                }
+                store_run(hist, h0, per, NB, cv);
+                if (lane == 63) hist[NB] = incl;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 4 * R; ++e)
+                if (sl[e] != 0xFFFFFFFFu) s[hist[xs[e] >> shift] + sl[e]] = xs[e];
+        }
+        __syncthreads();
+        const uint32_t V = hist[NB];
+        // The array is now ordered by bucket.  Sort by value: every lane sorts
+        // its PL consecutive keys in registers (bitonic network), then the
+        // windows shifted by PL/2 (any bucket of <= PL/2 + 1 keys lying across
+        // a window boundary falls inside one shifted window); a check pass
+        // counts repeats and repeats both passes in the rare case that a
+        // longer bucket left the order broken.
+        uint32_t ndup = 0;
+        {
+            const uint32_t R = V <= 512 ? 1 : 2;
+            const uint32_t span = 512 * R + 4;
+            for (uint32_t p = V + lane; p < span; p += 64) s[p] = 0xFFFFFFFFu;
+            for (;;) {
+                __syncthreads();
+                const uint32_t r = window_passes(s, V, R);
+                ndup = r >> 1;
+                if (!__syncthreads_or(r & 1)) break;
+            }
+        }
+        ndup = wave_sum32(ndup);
+        __syncthreads();
+        const uint32_t D = V - ndup;
+        if (D == ke) {
+            if (ndup) {
+                uint32_t kept = 0;
+                for (uint32_t b0 = 0; b0 < V; b0 += 64) {
+                    const uint32_t p = b0 + lane;
+                    uint32_t x = 0;
+                    bool keep = false;
+                    if (p < V) {
+                        x = s[p];
+                        keep = p == 0 || s[p - 1] != x;
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    __syncthreads();
+                    if (keep) s[kept + __popcll(bal & lanemask_lt(lane))] = x;
+                    kept += __popcll(bal);
+                    __syncthreads();
+                }
+            }
+            return true;
+        }
+        J += ke - D;
+    }
+}
+
 // Base case of the sampler for one tile: the sorted set of k distinct slots
 // of [0, S) obtained by drawing until k distinct values are seen (the draws
 // that reach k distinct values are found by growing J: each draw adds at
@@ -520,6 +844,14 @@ __device__ void leaf_sample(const TileCtx &t, uint32_t *s, uint32_t *hist, uint6
         emit_complement(t, s, 0, 0, t.S, 0);
         return;
     }
+    if (ke <= cap && leaf_fast<CAP>(t, s, hist, (uint32_t)ke, cap)) {
+        if (!comp) emit_sorted(t, s, (uint32_t)ke);
+        else {
+            emit_complement(t, s, (uint32_t)ke, 0, t.S, 0);
+        }
+        return;
+    }
+    __syncthreads();
     const uint64_t span = 1ull << t.bits;
     uint64_t nsub = 1;
     while (nsub < span && nsub * cap < ke) nsub <<= 1;
@@ -567,33 +899,75 @@ __device__ void leaf_sample(const TileCtx &t, uint32_t *s, uint32_t *hist, uint6
 template <int CAP>
 __global__ __launch_bounds__(64) void sample_kernel(Job job)
 {
-    __shared__ uint32_t s_bkt[CAP];
-    __shared__ uint32_t s_hist[CAP / 2 + 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_bkt[CAP + 8];
+    __shared__ __attribute__((aligned(16))) uint32_t s_hist[CAP + 8];
     if (job.status[1]) return;
     const uint64_t T = job.status[2];
     const uint64_t W = gridDim.x;
     const uint64_t per = (T + W - 1) / W;
     const uint64_t t0 = (uint64_t)blockIdx.x * per;
     const uint64_t t1 = t0 + per < T ? t0 + per : T;
-    uint64_t g = ~0ull, gend = 0, gstart = 0;
+    if (t0 >= t1) return;
+    const uint32_t cap = job.leaf_cap < CAP ? job.leaf_cap : CAP;
+    uint64_t gend = 0, gstart = 0, c = 0, prev_tl = 0;
+    bool prev_ok = false;     // prev_tl is the previous tile of this chunk
+    uint64_t qs = 0, rs = 0;        // 2^s = qs * dv + rs
+    uint32_t s = 0;
     Inst I;
     Chunk ch;
-    uint64_t c = 0;
+    Decoder dd;
+    dd.type = 0; dd.pow2 = 0; dd.sh = 0; dd.small = 0; dd.dv = 1; dd.rcp = 1.0;
+    dd.u0 = dd.w0 = dd.a = dd.b = dd.c0 = dd.h = dd.Ttri = dd.lbase = 0;
+    bool have = false;
+    uint64_t o_next = uni64(job.tile_off[t0]);
+    uint64_t o_pre = uni64(job.tile_off[t0 + 1]);
     for (uint64_t t = t0; t < t1; ++t) {
-        const uint64_t o0 = job.tile_off[t];
-        const uint64_t k = job.tile_off[t + 1] - o0;
+        const uint64_t o0 = o_next;
+        o_next = o_pre;
+        if (t + 2 <= T) o_pre = uni64(job.tile_off[t + 2]);   // one tile ahead
+        const uint64_t k = o_next - o0;
         if (k == 0) continue;
-        if (g == ~0ull || t >= gend) {
-            g = last_le(job.tstart, job.G, t);
-            gstart = job.tstart[g];
-            gend = job.tstart[g + 1];
+        if (!have || t >= gend) {
+            const uint64_t g = last_le(job.tstart, job.G, t);
+            gstart = uni64(job.tstart[g]);
+            gend = uni64(job.tstart[g + 1]);
             I = inst_at(job, inst_of_chunk(job, g));
-            c = g - I.chunk_base;
+            c = uni64(g - I.chunk_base);
             ch = chunk_geometry(I, c);
+            s = uni(I.s);
+            prev_ok = false;
+            have = true;
+            if (I.directed) { dd.type = 0; dd.dv = I.n - 1; }
+            else if (!ch.diag) { dd.type = 1; dd.dv = ch.w; dd.b = ch.b; }
+            else { dd.type = 2; dd.dv = 1; dd.h = ch.h; dd.Ttri = ch.N; }
+            dd.type = uni(dd.type);
+            dd.dv = uni64(dd.dv);
+            dd.pow2 = uni((dd.dv & (dd.dv - 1)) == 0);
+            dd.sh = uni(63 - __clzll(dd.dv));
+            dd.rcp = unid(1.0 / (double)dd.dv);
+            qs = uni64((1ull << s) / dd.dv);
+            rs = uni64((1ull << s) - qs * dd.dv);
         }
         const uint64_t tl = t - gstart;
-        const uint32_t s = I.s;
         const uint64_t lstart = tl << s;
+        if (dd.type == 2) {
+            dd.a = ch.a;
+            dd.lbase = lstart;
+        } else if (prev_ok && tl == prev_tl + 1) {
+            // next tile of the same chunk: advance by 2^s = qs * dv + rs
+            uint64_t w = (dd.type == 0 ? dd.w0 : dd.c0) + rs;
+            uint64_t q = qs;
+            if (w >= dd.dv) { w -= dd.dv; ++q; }
+            if (dd.type == 0) { dd.w0 = w; dd.u0 += q; } else { dd.c0 = w; dd.a += q; }
+        } else {
+            const uint64_t q = lstart / dd.dv;
+            const uint64_t r = lstart - q * dd.dv;
+            if (dd.type == 0) { dd.u0 = ch.row0 + q; dd.w0 = r; } else { dd.a = ch.a + q; dd.c0 = r; }
+        }
+        dd.u0 = uni64(dd.u0); dd.w0 = uni64(dd.w0); dd.a = uni64(dd.a); dd.c0 = uni64(dd.c0);
+        dd.lbase = uni64(dd.lbase);
+        prev_tl = tl;
+        prev_ok = true;
         TileCtx tc;
         tc.S = uni64((ch.N - lstart) < (1ull << s) ? (ch.N - lstart) : (1ull << s));
         tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
@@ -601,38 +975,11 @@ __global__ __launch_bounds__(64) void sample_kernel(Job job)
         tc.full = uni(tc.S == (1ull << tc.bits));
         tc.st = Stream{uni((uint32_t)I.seed), uni((uint32_t)(I.seed >> 32)), uni((uint32_t)c), uni((uint32_t)tl),
                        TAG_TLEAF};
-        tc.o0 = uni64(o0);
+        tc.o0 = o0;
         tc.edges = job.edges;
-        Decoder &dd = tc.dec;
-        dd.type = 0; dd.dv = 1; dd.rcp = 1.0; dd.u0 = dd.w0 = dd.a = dd.b = dd.c0 = dd.h = dd.Ttri = dd.lbase = 0;
-        if (I.directed) {
-            dd.type = 0;
-            dd.dv = I.n - 1;
-            dd.rcp = 1.0 / (double)dd.dv;
-            const uint64_t bi = ch.row0 * dd.dv + lstart;
-            dd.u0 = bi / dd.dv;
-            dd.w0 = bi - dd.u0 * dd.dv;
-        } else if (!ch.diag) {
-            dd.type = 1;
-            dd.dv = ch.w;
-            dd.rcp = 1.0 / (double)dd.dv;
-            const uint64_t r0 = lstart / ch.w;
-            dd.c0 = lstart - r0 * ch.w;
-            dd.a = ch.a + r0;
-            dd.b = ch.b;
-        } else {
-            dd.type = 2;
-            dd.h = ch.h;
-            dd.a = ch.a;
-            dd.Ttri = ch.N;
-            dd.lbase = lstart;
-        }
-        dd.type = uni(dd.type);
-        dd.dv = uni64(dd.dv); dd.rcp = unid(dd.rcp);
-        dd.u0 = uni64(dd.u0); dd.w0 = uni64(dd.w0);
-        dd.a = uni64(dd.a); dd.b = uni64(dd.b); dd.c0 = uni64(dd.c0);
-        dd.h = uni64(dd.h); dd.Ttri = uni64(dd.Ttri); dd.lbase = uni64(dd.lbase);
-        leaf_sample<CAP>(tc, s_bkt, s_hist, k, job.leaf_cap < CAP ? job.leaf_cap : CAP);
+        dd.small = uni((dd.type == 0 ? dd.w0 : dd.c0) + tc.S <= (1ull << 32));
+        tc.dec = dd;
+        leaf_sample<CAP>(tc, s_bkt, s_hist, k, cap);
         __syncthreads();
     }
 }

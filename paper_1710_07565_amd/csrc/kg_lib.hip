@@ -55,12 +55,13 @@ struct KernelTimer {
     }
 };
 
-constexpr int64_t kDefaultSampleWaves = 16;
-constexpr int64_t kDefaultPlanWaves = 16;
 
 std::mutex g_init_mu;
 bool g_init_done[64];
 int g_num_cu[64];
+
+int g_sample_blocks_per_cu[64];
+int g_plan_blocks_per_cu[64];
 
 kg_status ensure_init(int *dev_out)
 {
@@ -72,6 +73,14 @@ kg_status ensure_init(int *dev_out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return KG_EDEVICE;
     g_num_cu[dev] = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    // resident one-wave workgroups per compute unit: a grid of exactly that
+    // many avoids a partial second round of workgroups
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel<kCapMax>, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    g_sample_blocks_per_cu[dev] = nb;
+    nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    g_plan_blocks_per_cu[dev] = nb;
     hipLaunchKernelGGL(lnf_init_kernel, dim3(1), dim3(64), 0, 0);
     if (hipGetLastError() != hipSuccess) return KG_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return KG_EDEVICE;
@@ -195,6 +204,14 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     if (cap > kCapMax) cap = kCapMax;
     if (cap < 128) cap = 128;
     job.leaf_cap = (uint32_t)cap;
+    // planner units: enough of them to give every resident lane one (one lane
+    // expands a unit), at most kUnitTiles tiles each
+    {
+        const uint64_t lanes = 256ull * 8 * 64;
+        uint32_t ulog = 1;
+        while (ulog < 6 && (P.Tb >> (ulog + 1)) >= lanes) ++ulog;
+        job.unit_log = ulog;
+    }
     job.G = P.G;
     job.capacity = capacity;
     job.tile_cap = P.Tb;
@@ -234,14 +251,15 @@ kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s)
 kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
 {
     const int64_t cu = g_num_cu[dev];
-    const uint64_t ub = 2 * (P.Tb / kUnitTiles) + P.G + 1;   // bound on planner units
-    uint64_t pgrid = (uint64_t)(cu * opt_or(g_plan_waves, kDefaultPlanWaves));
-    if (pgrid > ub) pgrid = ub;
+    // planner units: at most 2 per 2^unit_log tiles plus one per chunk; one lane each
+    const uint64_t ub = 2 * (P.Tb >> job.unit_log) + P.G + 1;
+    uint64_t pgrid = (uint64_t)(cu * opt_or(g_plan_waves, g_plan_blocks_per_cu[dev]));
+    if (pgrid > (ub + 63) / 64) pgrid = (ub + 63) / 64;
     {
         KernelTimer tm(KG_KERNEL_PLAN, s);
         hipLaunchKernelGGL(plan_kernel, dim3((uint32_t)pgrid), dim3(64), 0, s, job);
     }
-    uint64_t sgrid = (uint64_t)(cu * opt_or(g_sample_waves, kDefaultSampleWaves));
+    uint64_t sgrid = (uint64_t)(cu * opt_or(g_sample_waves, g_sample_blocks_per_cu[dev]));
     if (sgrid > P.Tb + 1) sgrid = P.Tb + 1;
     {
         KernelTimer tm(KG_KERNEL_SAMPLE, s);
@@ -459,8 +477,8 @@ int64_t kg_get_option(int option)
 {
     switch (option) {
     case KG_OPT_LEAF_CAP: return opt_or(g_leaf_cap, kCapMax);
-    case KG_OPT_SAMPLE_WAVES: return opt_or(g_sample_waves, kDefaultSampleWaves);
-    case KG_OPT_PLAN_WAVES: return opt_or(g_plan_waves, kDefaultPlanWaves);
+    case KG_OPT_SAMPLE_WAVES: return g_sample_waves;     // 0: as many as fit on a compute unit
+    case KG_OPT_PLAN_WAVES: return g_plan_waves;
     case KG_OPT_TIME_KERNELS: return g_time_kernels;
     default: return -1;
     }

@@ -89,7 +89,7 @@ def test_generation_calls_reject_bad_arguments_without_a_device(L):
     assert L.kg_set_option(1, 4096) == _lib.KG_ERANGE
     assert L.kg_set_option(42, 1) == _lib.KG_EINVAL
     assert L.kg_set_option(2, 8) == 0 and L.kg_get_option(2) == 8
-    assert L.kg_set_option(2, 0) == 0 and L.kg_get_option(2) == 16
+    assert L.kg_set_option(2, 0) == 0 and L.kg_get_option(2) == 0
 
 
 def test_oracle_tile_exponent_is_minimal(kgref):

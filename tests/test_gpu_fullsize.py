@@ -1,0 +1,121 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: every chunk count equals the oracle's, a spread of whole chunks
+(first, last, diagonal, random) equals the oracle byte for byte, and
+properties that hold at any size are checked over the entire output on the
+device (count, id range, u < v when undirected, ascending inside each chunk,
+no repeats)."""
+import numpy as np
+import pytest
+
+from gpu_util import require_gpu, to_np_u32, to_np_u64
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_whole_output(torch, E, offs, n, directed):
+    """Invariants on the device, in slices (E is (edges, 2) uint32)."""
+    Ei = E.view(torch.int32)                  # ids < 2^31 here: int32 order = uint32 order
+    total = E.shape[0]
+    step = 1 << 27
+    bounds = torch.from_numpy(offs.astype(np.int64)).cuda()
+    for a in range(0, total, step):
+        b = min(total, a + step)
+        u = Ei[a:b, 0].to(torch.int64)
+        v = Ei[a:b, 1].to(torch.int64)
+        assert int(u.min()) >= 0 and int(v.min()) >= 0
+        assert int(u.max()) < n and int(v.max()) < n
+        assert not bool((u == v).any())
+        if not directed:
+            assert bool((u < v).all())
+        key = u * n + v
+        del u, v
+        # ascending inside chunks: a step down may only happen at a chunk start
+        dif = key[1:] - key[:-1]
+        bad = torch.nonzero(dif <= 0).flatten() + (a + 1)
+        if bad.numel():
+            starts = torch.isin(bad, bounds)
+            assert bool(starts.all()), "order broken inside a chunk at %s" % bad[~starts][:5].tolist()
+        del key, dif
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_undirected_gnm_n26_m31(kgref, seed):
+    import torch
+    kg = require_gpu()
+    n, m, P = 2**26, 2**31, 256
+    E = kg.gnm(n, m, False, seed, P)
+    counts = to_np_u64(kg.chunk_counts(kg.Instance(n, kg.GNM, False, m, 0.0, seed, P)))
+    torch.cuda.synchronize()
+    I = kgref.inst(n, m=m, directed=False, seed=seed, chunks=P)
+    want_counts = kgref.chunk_counts(I)
+    assert np.array_equal(counts, want_counts)
+    offs = np.concatenate([[0], np.cumsum(want_counts.astype(np.int64))])
+    assert offs[-1] == m
+    C = len(want_counts)
+    rng = np.random.default_rng(seed)
+    diag = [P * i - i * (i - 1) // 2 for i in (0, 1, 100, 255)]
+    sample = sorted(set([0, 1, C - 1, C // 2] + diag + list(rng.integers(0, C, 10))))
+    for c in sample:
+        got = to_np_u32(E[offs[c]:offs[c + 1]])
+        want = kgref.chunk_edges(I, int(c), int(want_counts[c]))
+        assert np.array_equal(got, want), "chunk %d" % c
+    _check_whole_output(torch, E, offs, n, False)
+    del E
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("directed,P,deg", [(True, 2**16, 16.0), (False, 256, 64.0)])
+def test_gnp_n25(kgref, directed, P, deg):
+    import torch
+    kg = require_gpu()
+    n, seed = 2**25, 1
+    p = deg / (n - 1)
+    E = kg.gnp(n, p, directed, seed, P)
+    counts = to_np_u64(kg.chunk_counts(kg.Instance(n, kg.GNP, directed, 0, p, seed, P)))
+    torch.cuda.synchronize()
+    I = kgref.inst(n, p=p, directed=directed, seed=seed, chunks=P, model=1)
+    want_counts = kgref.chunk_counts(I)
+    assert np.array_equal(counts, want_counts)
+    offs = np.concatenate([[0], np.cumsum(want_counts.astype(np.int64))])
+    assert offs[-1] == E.shape[0]
+    C = len(want_counts)
+    rng = np.random.default_rng(7)
+    sample = sorted(set([0, C - 1, C // 3] + list(rng.integers(0, C, 10))))
+    for c in sample:
+        got = to_np_u32(E[offs[c]:offs[c + 1]])
+        want = kgref.chunk_edges(I, int(c), int(want_counts[c]))
+        assert np.array_equal(got, want), "chunk %d" % c
+    _check_whole_output(torch, E, offs, n, directed)
+    del E
+    torch.cuda.empty_cache()
+
+
+def test_batched_workload_sample(kgref):
+    """Instances drawn by the batched workload's recipe (n log-uniform in
+    [2^10, 2^22], mean degree in [2, 64], half directed, half G(n,m)), in one
+    kg_batch pass: small instances against the oracle in full, large ones on
+    sampled chunks, every instance against its own single call."""
+    import torch
+    kg = require_gpu()
+    from paper_1710_07565_amd import workloads
+    specs = workloads.batch_instances(count=96, base_seed=1, seed_fn=kg.instance_seed)
+    insts = [kg.Instance(s.n, s.model, s.directed, s.m, s.p, s.seed, s.chunks) for s in specs]
+    arena, offs = kg.batch(insts)
+    torch.cuda.synchronize()
+    O = to_np_u64(offs).astype(np.int64)
+    for i, (s, I) in enumerate(zip(specs, insts)):
+        seg = arena[O[i]:O[i + 1]]
+        if I.model == kg.GNM:
+            alone = kg.gnm(I.n, I.m, I.directed, I.seed, I.chunks)
+        else:
+            alone = kg.gnp(I.n, I.p, I.directed, I.seed, I.chunks)
+        assert torch.equal(seg.view(torch.int32), alone.view(torch.int32)), i
+        del alone
+        ref = kgref.inst(s.n, m=s.m, p=s.p, directed=s.directed, seed=s.seed, chunks=s.chunks, model=s.model)
+        if s.n <= 2**16:
+            assert np.array_equal(to_np_u32(seg), kgref.generate(ref)), i
+        else:
+            cnt = kgref.chunk_counts(ref)
+            co = np.concatenate([[0], np.cumsum(cnt.astype(np.int64))])
+            for c in sorted(set([0, len(cnt) - 1])):
+                assert np.array_equal(to_np_u32(seg[co[c]:co[c + 1]]), kgref.chunk_edges(ref, c, int(cnt[c]))), i

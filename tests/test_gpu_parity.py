@@ -111,16 +111,19 @@ def test_leaf_capacity_does_not_change_bits(kg, kgref, cap):
 
 @pytest.mark.parametrize("sw,pw", [(1, 1), (3, 2), (32, 64)])
 def test_launch_shape_does_not_change_bits(kg, sw, pw):
-    """The chunk -> workgroup mapping must not show in the output."""
+    """The tile -> workgroup mapping must not show in the output."""
     base = gpu_gnm(kg, 5000, 10**6, False, 3, 33)
+    base2 = gpu_gnm(kg, 2**14, 2**21, True, 4, 1)
     try:
         kg.set_option(kg._lib.KG_OPT_SAMPLE_WAVES, sw)
         kg.set_option(kg._lib.KG_OPT_PLAN_WAVES, pw)
         got = gpu_gnm(kg, 5000, 10**6, False, 3, 33)
+        got2 = gpu_gnm(kg, 2**14, 2**21, True, 4, 1)
     finally:
         kg.set_option(kg._lib.KG_OPT_SAMPLE_WAVES, 0)
         kg.set_option(kg._lib.KG_OPT_PLAN_WAVES, 0)
     check_equal(got, base, "launch shape %d/%d" % (sw, pw))
+    check_equal(got2, base2, "launch shape %d/%d" % (sw, pw))
 
 
 @pytest.mark.parametrize("n,directed,P,model", [(2**16, True, 64, 0), (2**26, False, 256, 0),
