@@ -26,7 +26,8 @@ struct Job {
     uint64_t *tstart;        // G + 1: tiles per chunk, then first tile
     uint64_t *ustart;        // G + 1: planner units per chunk, then first unit
     uint64_t *tile_off;      // output offset of every tile, + total
-    uint64_t *status;        // [0] edges [1] overflow [2] tiles [3] units
+    uint64_t *status;        // [0] edges [1] overflow [2] tiles [3] units [4] queued tiles
+    uint64_t *queue;         // tile_cap entries: tiles left to the general base case
     uint64_t *out_total;     // optional: edge total
     uint64_t *inst_off;      // optional: ninst + 1 instance offsets
     uint32_t *edges;
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(Job job)
         job.off[G] = E; job.tstart[G] = T; job.ustart[G] = U;
         const uint64_t overflow = (E > job.capacity || T > job.tile_cap) ? 1 : 0;
         job.status[0] = E; job.status[1] = overflow; job.status[2] = T; job.status[3] = U;
+        job.status[4] = 0;
         if (T <= job.tile_cap) job.tile_off[T] = E;
         if (job.out_total) *job.out_total = E;
     }
@@ -276,6 +278,20 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v)
     return v;
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP moves: shifts by 1, 2, 4
+// and 8 inside rows of 16 lanes, then the last lane of row 0 / 2 is added to
+// row 1 / 3 and the last lane of row 1 to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
 {
 #pragma unroll
@@ -285,57 +301,54 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
 
 // Slot -> edge of one tile (Sec. 4.1 and 4.2 offset computations).
 // Directed: slot w of row u (w in [0, n-1)) is column w + [w >= u].
-// Rectangle: local l -> (row a + l / width, column b + l % width).
+// Rectangle: local l -> (row r0 + l / width, column b + l % width).
 // Triangle: rows counted from the bottom hold 1, 2, 3, ... slots.
-// The divisions by n - 1 or by the section width use a binary64 reciprocal
-// estimate corrected by one step (exact for dividends below 2^33), or a shift
-// when the divisor is a power of two.
+// Because N < 2^53, n < 2^27: rows, columns, section sizes and the divisor
+// fit 32 bits.  The dividend c0 + x fits 32 bits unless the tile has close
+// to 2^32 slots ("wide").  Divisions use a binary64 reciprocal estimate
+// corrected by one step (exact for dividends below 2^33), or a shift when
+// the divisor is a power of two.
 struct Decoder {
     uint32_t type;      // 0 directed, 1 rectangle, 2 triangle
     uint32_t pow2;      // divisor is 2^sh
     uint32_t sh;
-    uint32_t small;     // every dividend of the tile fits 32 bits
-    uint64_t dv;        // directed: n - 1; rectangle: section width
+    uint32_t wide;      // some dividend c0 + x of the tile needs 33 bits
+    uint32_t dv;        // directed: n - 1; rectangle: section width
+    uint32_t r0, c0;    // row of the tile start and its offset in that row
+    uint32_t b;         // rectangle: first column
+    uint32_t a, h;      // triangle: section start and size
     double rcp;         // 1 / dv
-    uint64_t u0, w0;    // directed: row / slot in row of the tile start
-    uint64_t a, b, c0;  // rectangle: row of the tile start, first column, column of the tile start
-    uint64_t h, Ttri, lbase;  // triangle: section size, its slots, tile start
+    uint64_t Ttri, lbase;  // triangle: its slots, tile start
 
-    __device__ __forceinline__ uint64_t divmod(uint64_t x, uint64_t &rem) const
+    __device__ __forceinline__ uint32_t divmod(uint32_t x, uint32_t &rem) const
     {
-        if (pow2) {
-            rem = x & (dv - 1);
-            return x >> sh;
-        }
-        if (small) {
-            const uint32_t x32 = (uint32_t)x, d32 = (uint32_t)dv;
-            uint32_t q = (uint32_t)((double)x32 * rcp);
-            int32_t r = (int32_t)(x32 - q * d32);
-            if (r < 0) { --q; r += (int32_t)d32; }
-            else if ((uint32_t)r >= d32) { ++q; r -= (int32_t)d32; }
+        if (!wide) {
+            const uint32_t y = c0 + x;
+            if (pow2) { rem = y & (dv - 1); return y >> sh; }
+            uint32_t q = (uint32_t)((double)y * rcp);
+            int32_t r = (int32_t)(y - q * dv);
+            if (r < 0) { --q; r += (int32_t)dv; }
+            else if ((uint32_t)r >= dv) { ++q; r -= (int32_t)dv; }
             rem = (uint32_t)r;
             return q;
         }
-        uint64_t q = (uint64_t)((double)x * rcp);
-        int64_t r = (int64_t)(x - q * dv);
+        const uint64_t y = (uint64_t)c0 + x;
+        if (pow2) { rem = (uint32_t)(y & (dv - 1)); return (uint32_t)(y >> sh); }
+        uint64_t q = (uint64_t)((double)y * rcp);
+        int64_t r = (int64_t)(y - q * dv);
         if (r < 0) { --q; r += (int64_t)dv; }
         else if ((uint64_t)r >= dv) { ++q; r -= (int64_t)dv; }
-        rem = (uint64_t)r;
-        return q;
+        rem = (uint32_t)r;
+        return (uint32_t)q;
     }
 
     __device__ __forceinline__ uint2 operator()(uint32_t x) const
     {
-        if (type == 0) {
-            uint64_t r;
-            const uint64_t q = divmod(w0 + x, r);
-            const uint64_t u = u0 + q;
-            return make_uint2((uint32_t)u, (uint32_t)(r + (r >= u)));
-        }
-        if (type == 1) {
-            uint64_t r;
-            const uint64_t q = divmod(c0 + x, r);
-            return make_uint2((uint32_t)(a + q), (uint32_t)(b + r));
+        if (type != 2) {
+            uint32_t r;
+            const uint32_t q = divmod(x, r);
+            const uint32_t u = r0 + q;
+            return type == 0 ? make_uint2(u, r + (r >= u)) : make_uint2(u, b + r);
         }
         const uint64_t l = lbase + x;
         const uint64_t lr = Ttri - 1 - l;
@@ -892,94 +905,6 @@ __device__ void leaf_sample(const TileCtx &t, uint32_t *s, uint32_t *hist, uint6
         const uint32_t n = collect_sorted<CAP>(t, s, hist, J, sb * W, (sb + 1) * W, cap);
         const uint64_t hi = (sb + 1) * W < t.S ? (sb + 1) * W : t.S;
         if (sb * W < hi) r += emit_complement(t, s, n, sb * W, hi, r);
-        __syncthreads();
-    }
-}
-
-template <int CAP>
-__global__ __launch_bounds__(64) void sample_kernel(Job job)
-{
-    __shared__ __attribute__((aligned(16))) uint32_t s_bkt[CAP + 8];
-    __shared__ __attribute__((aligned(16))) uint32_t s_hist[CAP + 8];
-    if (job.status[1]) return;
-    const uint64_t T = job.status[2];
-    const uint64_t W = gridDim.x;
-    const uint64_t per = (T + W - 1) / W;
-    const uint64_t t0 = (uint64_t)blockIdx.x * per;
-    const uint64_t t1 = t0 + per < T ? t0 + per : T;
-    if (t0 >= t1) return;
-    const uint32_t cap = job.leaf_cap < CAP ? job.leaf_cap : CAP;
-    uint64_t gend = 0, gstart = 0, c = 0, prev_tl = 0;
-    bool prev_ok = false;     // prev_tl is the previous tile of this chunk
-    uint64_t qs = 0, rs = 0;        // 2^s = qs * dv + rs
-    uint32_t s = 0;
-    Inst I;
-    Chunk ch;
-    Decoder dd;
-    dd.type = 0; dd.pow2 = 0; dd.sh = 0; dd.small = 0; dd.dv = 1; dd.rcp = 1.0;
-    dd.u0 = dd.w0 = dd.a = dd.b = dd.c0 = dd.h = dd.Ttri = dd.lbase = 0;
-    bool have = false;
-    uint64_t o_next = uni64(job.tile_off[t0]);
-    uint64_t o_pre = uni64(job.tile_off[t0 + 1]);
-    for (uint64_t t = t0; t < t1; ++t) {
-        const uint64_t o0 = o_next;
-        o_next = o_pre;
-        if (t + 2 <= T) o_pre = uni64(job.tile_off[t + 2]);   // one tile ahead
-        const uint64_t k = o_next - o0;
-        if (k == 0) continue;
-        if (!have || t >= gend) {
-            const uint64_t g = last_le(job.tstart, job.G, t);
-            gstart = uni64(job.tstart[g]);
-            gend = uni64(job.tstart[g + 1]);
-            I = inst_at(job, inst_of_chunk(job, g));
-            c = uni64(g - I.chunk_base);
-            ch = chunk_geometry(I, c);
-            s = uni(I.s);
-            prev_ok = false;
-            have = true;
-            if (I.directed) { dd.type = 0; dd.dv = I.n - 1; }
-            else if (!ch.diag) { dd.type = 1; dd.dv = ch.w; dd.b = ch.b; }
-            else { dd.type = 2; dd.dv = 1; dd.h = ch.h; dd.Ttri = ch.N; }
-            dd.type = uni(dd.type);
-            dd.dv = uni64(dd.dv);
-            dd.pow2 = uni((dd.dv & (dd.dv - 1)) == 0);
-            dd.sh = uni(63 - __clzll(dd.dv));
-            dd.rcp = unid(1.0 / (double)dd.dv);
-            qs = uni64((1ull << s) / dd.dv);
-            rs = uni64((1ull << s) - qs * dd.dv);
-        }
-        const uint64_t tl = t - gstart;
-        const uint64_t lstart = tl << s;
-        if (dd.type == 2) {
-            dd.a = ch.a;
-            dd.lbase = lstart;
-        } else if (prev_ok && tl == prev_tl + 1) {
-            // next tile of the same chunk: advance by 2^s = qs * dv + rs
-            uint64_t w = (dd.type == 0 ? dd.w0 : dd.c0) + rs;
-            uint64_t q = qs;
-            if (w >= dd.dv) { w -= dd.dv; ++q; }
-            if (dd.type == 0) { dd.w0 = w; dd.u0 += q; } else { dd.c0 = w; dd.a += q; }
-        } else {
-            const uint64_t q = lstart / dd.dv;
-            const uint64_t r = lstart - q * dd.dv;
-            if (dd.type == 0) { dd.u0 = ch.row0 + q; dd.w0 = r; } else { dd.a = ch.a + q; dd.c0 = r; }
-        }
-        dd.u0 = uni64(dd.u0); dd.w0 = uni64(dd.w0); dd.a = uni64(dd.a); dd.c0 = uni64(dd.c0);
-        dd.lbase = uni64(dd.lbase);
-        prev_tl = tl;
-        prev_ok = true;
-        TileCtx tc;
-        tc.S = uni64((ch.N - lstart) < (1ull << s) ? (ch.N - lstart) : (1ull << s));
-        tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
-        tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
-        tc.full = uni(tc.S == (1ull << tc.bits));
-        tc.st = Stream{uni((uint32_t)I.seed), uni((uint32_t)(I.seed >> 32)), uni((uint32_t)c), uni((uint32_t)tl),
-                       TAG_TLEAF};
-        tc.o0 = o0;
-        tc.edges = job.edges;
-        dd.small = uni((dd.type == 0 ? dd.w0 : dd.c0) + tc.S <= (1ull << 32));
-        tc.dec = dd;
-        leaf_sample<CAP>(tc, s_bkt, s_hist, k, cap);
         __syncthreads();
     }
 }

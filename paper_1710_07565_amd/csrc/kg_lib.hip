@@ -12,7 +12,7 @@
 #include <vector>
 
 #include "../../include/kg.h"
-#include "kg_kernels.hpp"
+#include "kg_tile.hpp"
 
 namespace kg {
 __device__ double g_lnf_tab[kLnfTab + 1];
@@ -76,7 +76,7 @@ kg_status ensure_init(int *dev_out)
     // resident one-wave workgroups per compute unit: a grid of exactly that
     // many avoids a partial second round of workgroups
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel<kCapMax>, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_sample_blocks_per_cu[dev] = nb;
     nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
@@ -124,7 +124,7 @@ kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
 }
 
 struct Layout {
-    uint64_t status, insts, off, tstart, ustart, tile_off, total;
+    uint64_t status, insts, off, tstart, ustart, tile_off, queue, total;
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -139,6 +139,7 @@ Layout layout_for(uint32_t ninst, uint64_t G, uint64_t Tb)
     L.tstart = o; o = align256(o + (G + 1) * 8);
     L.ustart = o; o = align256(o + (G + 1) * 8);
     L.tile_off = o; o = align256(o + (Tb + 1) * 8);
+    L.queue = o; o = align256(o + (Tb + 1) * 8);
     L.total = o;
     return L;
 }
@@ -222,6 +223,7 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     job.ustart = (uint64_t *)(ws.base + P.L.ustart);
     job.tile_off = (uint64_t *)(ws.base + P.L.tile_off);
     job.status = (uint64_t *)(ws.base + P.L.status);
+    job.queue = (uint64_t *)(ws.base + P.L.queue);
     job.edges = edges;
     return job;
 }
@@ -261,9 +263,14 @@ kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
     }
     uint64_t sgrid = (uint64_t)(cu * opt_or(g_sample_waves, g_sample_blocks_per_cu[dev]));
     if (sgrid > P.Tb + 1) sgrid = P.Tb + 1;
+    // tiles the fast kernel queues are rare; a grid of one wave per compute
+    // unit drains the queue (it exits at once when the queue is empty)
+    uint64_t qgrid = (uint64_t)cu;
+    if (qgrid > P.Tb + 1) qgrid = P.Tb + 1;
     {
         KernelTimer tm(KG_KERNEL_SAMPLE, s);
-        hipLaunchKernelGGL(sample_kernel<kCapMax>, dim3((uint32_t)sgrid), dim3(64), 0, s, job);
+        hipLaunchKernelGGL(tile_kernel, dim3((uint32_t)sgrid), dim3(64), 0, s, job);
+        hipLaunchKernelGGL(queue_kernel<kCapMax>, dim3((uint32_t)qgrid), dim3(64), 0, s, job);
     }
     return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
 }

@@ -1,0 +1,433 @@
+// kg_tile.hpp -- the sampler's two kernels.
+//
+//   tile_kernel  : the common case.  One wavefront per tile; a tile whose
+//                  base case needs at most kFastDraws draws keeps them in
+//                  registers (16 per lane), sorts them in LDS and streams the
+//                  decoded edges out.  Any other tile is appended to a queue.
+//   queue_kernel : the queued tiles, with the general base case (key
+//                  sub-ranges when the draws exceed the LDS capacity).
+//
+// Both produce the same bits for a tile: the sorted distinct set of the
+// first J draws of the tile's stream with J the smallest count giving k
+// distinct valid values (Sec. 2.2 base case; Sec. 4.1, 4.2 offsets).
+#pragma once
+#include "kg_kernels.hpp"
+
+namespace kg {
+
+constexpr uint32_t kFastDraws = 1024;   // draws one wave keeps in registers
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Wave-uniform 64-bit load through the scalar data cache.  Only for data
+// that no lane writes while the kernel runs (sizes and offsets written by
+// the earlier kernels of the pass).
+__device__ __forceinline__ uint64_t ld_uni(const uint64_t *p)
+{
+    return *(const __attribute__((address_space(4))) uint64_t *)p;
+}
+
+// Consecutive tiles of one wave: the chunk is looked up when a tile leaves
+// the current one, and the decoding constants of a tile are advanced from
+// those of the previous tile of the same chunk.  The tile context (slots,
+// stream, decoder) lives here and is updated in place.
+struct TileWalk {
+    uint64_t g, gstart, gend;   // current chunk, its first tile, first tile of the next
+    uint64_t N;                 // slots of the chunk
+    uint64_t qs;                // 2^s = qs * dv + rs
+    uint64_t prev_tl;
+    uint32_t s;                 // tile exponent
+    uint32_t row0;              // first row of the chunk (directed) or its row section
+    uint32_t rs;
+    bool prev_ok, have;
+    TileCtx tc;
+
+    __device__ __forceinline__ void enter(const Job &job, uint64_t gg)
+    {
+        g = gg;
+        gstart = ld_uni(job.tstart + g);
+        gend = ld_uni(job.tstart + g + 1);
+        // the fields the sampler needs, through the scalar cache for batches
+        Inst I;
+        memset(&I, 0, sizeof(I));
+        if (job.ninst == 1) {
+            I.n = job.one.n; I.seed = job.one.seed; I.chunk_base = job.one.chunk_base;
+            I.directed = job.one.directed; I.P = job.one.P; I.s = job.one.s;
+        } else {
+            const __attribute__((address_space(4))) Inst *q =
+                (const __attribute__((address_space(4))) Inst *)(job.insts + inst_of_chunk(job, g));
+            I.n = q->n; I.seed = q->seed; I.chunk_base = q->chunk_base;
+            I.directed = q->directed; I.P = q->P; I.s = q->s;
+        }
+        const uint32_t c = uni((uint32_t)(g - I.chunk_base));
+        s = uni(I.s);
+        const Chunk ch = chunk_geometry(I, c);
+        N = uni64(ch.N);
+        Decoder &d = tc.dec;
+        d.r0 = d.c0 = d.b = d.a = d.h = 0;
+        d.Ttri = d.lbase = 0;
+        d.wide = 0;
+        uint64_t dv;
+        if (I.directed) {
+            d.type = 0; dv = I.n - 1; row0 = uni((uint32_t)ch.row0);
+        } else if (!ch.diag) {
+            d.type = 1; dv = ch.w; d.b = uni((uint32_t)ch.b); row0 = uni((uint32_t)ch.a);
+        } else {
+            d.type = 2; dv = 1; row0 = uni((uint32_t)ch.a);
+            d.a = row0; d.h = uni((uint32_t)ch.h); d.Ttri = N;
+        }
+        if (dv == 0) dv = 1;
+        d.type = uni(d.type);
+        d.dv = uni((uint32_t)dv);
+        d.pow2 = uni((dv & (dv - 1)) == 0);
+        d.sh = uni(63 - __clzll(dv));
+        d.rcp = unid(1.0 / (double)dv);
+        qs = uni64((1ull << s) / dv);
+        rs = uni((uint32_t)((1ull << s) - qs * dv));
+        tc.st = Stream{uni((uint32_t)I.seed), uni((uint32_t)(I.seed >> 32)), c, 0, TAG_TLEAF};
+        prev_ok = false;
+        have = true;
+    }
+
+    // chunk of tile t: binary search for the first tile of a wave, then a
+    // forward walk (chunks without tiles are stepped over)
+    __device__ __forceinline__ void locate(const Job &job, uint64_t t)
+    {
+        if (!have) {
+            uint64_t lo = 0, hi = job.G;
+            while (hi - lo > 1) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
+            }
+            enter(job, lo);
+            return;
+        }
+        if (t < gend) return;
+        uint64_t gg = g + 1;
+        while (ld_uni(job.tstart + gg + 1) <= t) ++gg;
+        enter(job, gg);
+    }
+
+    // slot count, stream counter and decoding constants of tile t (of the
+    // current chunk)
+    __device__ __forceinline__ void tile(uint64_t t)
+    {
+        Decoder &d = tc.dec;
+        const uint64_t tl = t - gstart;
+        const uint64_t lstart = tl << s;
+        if (d.type == 2) {
+            d.lbase = lstart;
+        } else if (prev_ok && tl == prev_tl + 1) {
+            // next tile of the chunk: advance by 2^s = qs * dv + rs
+            uint32_t w = d.c0 + rs;
+            uint32_t q = (uint32_t)qs;
+            if (w >= d.dv) { w -= d.dv; ++q; }
+            d.c0 = w;
+            d.r0 += q;
+        } else {
+            const uint64_t q = lstart / d.dv;
+            d.c0 = uni((uint32_t)(lstart - q * d.dv));
+            d.r0 = uni(row0 + (uint32_t)q);
+        }
+        d.lbase = uni64(d.lbase);
+        prev_tl = tl;
+        prev_ok = true;
+        tc.S = uni64((N - lstart) < (1ull << s) ? (N - lstart) : (1ull << s));
+        tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
+        tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
+        tc.full = uni(tc.S == (1ull << tc.bits));
+        tc.st.b = uni((uint32_t)tl);
+        d.wide = uni((uint64_t)d.c0 + tc.S > (1ull << 32));
+    }
+};
+
+// Base case of the common tiles.  Pass 1 (one Philox block per lane and
+// trip; lane L computes blocks L + 64 e, i.e. draws 256 e + 4 L + q) counts
+// every valid draw in its bucket -- the top min(10, bits) bits of the key,
+// 16-bit counters two to a word -- and stages the draws in s[] (rejected
+// ones as ~0).  An exclusive scan turns the counters into bucket starts.
+// Pass 2 reloads the staged draws and places each at a position taken from
+// its bucket start by an LDS atomic; the 8-key window passes then sort
+// inside buckets and count repeats.  While fewer than ke distinct values are
+// seen, J grows by the shortfall (each draw adds at most one new value).
+// Leaves the sorted set in s[0..ke) and returns true, or returns false once
+// J would exceed lim.
+constexpr uint32_t kBucketWords = 512;   // 1024 16-bit counters
+
+__device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t *cnt, uint32_t ke, uint32_t lim)
+{
+    const uint32_t lane = threadIdx.x;
+    const uint32_t S32 = (uint32_t)t.S;                 // used only when S < 2^bits <= 2^32
+    const uint32_t shift = t.bits > 10 ? t.bits - 10 : 0;
+    uint4 *cw = reinterpret_cast<uint4 *>(cnt) + 2 * lane;   // this lane's 8 counter words
+    uint32_t J = ke;
+    for (;;) {
+        if (J > lim) return false;
+        cw[0] = make_uint4(0, 0, 0, 0);
+        cw[1] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        const uint32_t nit = uni((J + 255) >> 8);
+#pragma unroll 1
+        for (uint32_t e = 0; e < nit; ++e) {
+            const uint32_t blk = lane + 64u * e;
+            const U4 w = t.st.block(blk);
+            uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = 4 * blk + q < J && (t.full || v[q] < S32);
+                if (ok) {
+                    const uint32_t b = v[q] >> shift;
+                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1) << 4));
+                } else {
+                    v[q] = kNone;
+                }
+            }
+            *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();
+        {
+            const uint4 c0 = cw[0], c1 = cw[1];
+            uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            uint32_t packed = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) packed += w[i];      // halves cannot carry: totals <= 1024
+            const uint32_t sum = (packed & 0xFFFFu) + (packed >> 16);
+            const uint32_t incl = wave_incl_scan32(sum);
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t lo = w[i] & 0xFFFFu, hi = w[i] >> 16;
+                w[i] = run | ((run + lo) << 16);
+                run += lo + hi;
+            }
+            cw[0] = make_uint4(w[0], w[1], w[2], w[3]);
+            cw[1] = make_uint4(w[4], w[5], w[6], w[7]);
+            if (lane == 63) cnt[kBucketWords] = incl;
+        }
+        __syncthreads();
+        {
+            // every staged draw is loaded before the first one is placed
+            uint32_t x[16];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint4 q = make_uint4(kNone, kNone, kNone, kNone);
+                if ((uint32_t)e < nit) q = *reinterpret_cast<const uint4 *>(s + 4 * (lane + 64 * e));
+                x[4 * e] = q.x; x[4 * e + 1] = q.y; x[4 * e + 2] = q.z; x[4 * e + 3] = q.w;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (x[i] != kNone) {
+                    const uint32_t b = x[i] >> shift, h = (b & 1) << 4;
+                    const uint32_t pos = (atomicAdd(&cnt[b >> 1], 1u << h) >> h) & 0xFFFFu;
+                    s[pos] = x[i];
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t V = uni(cnt[kBucketWords]);
+        uint32_t ndup = 0;
+        {
+            const uint32_t R = V <= 512 ? 1 : 2;
+            const uint32_t span = 512 * R + 4;
+            for (uint32_t p = V + lane; p < span; p += 64) s[p] = kNone;
+            for (;;) {
+                __syncthreads();
+                const uint32_t r = window_passes(s, V, R);
+                ndup = r >> 1;
+                if (!__syncthreads_or(r & 1)) break;
+            }
+        }
+        ndup = __builtin_amdgcn_readlane(wave_incl_scan32(ndup), 63);
+        __syncthreads();
+        const uint32_t D = V - ndup;
+        if (D == ke) {
+            if (ndup) {
+                uint32_t kept = 0;
+                for (uint32_t b0 = 0; b0 < V; b0 += 64) {
+                    const uint32_t p = b0 + lane;
+                    uint32_t xv = 0;
+                    bool keep = false;
+                    if (p < V) {
+                        xv = s[p];
+                        keep = p == 0 || s[p - 1] != xv;
+                    }
+                    const uint64_t bal = __ballot(keep);
+                    __syncthreads();
+                    if (keep) s[kept + __popcll(bal & lanemask_lt(lane))] = xv;
+                    kept += __popcll(bal);
+                    __syncthreads();
+                }
+            }
+            return true;
+        }
+        J += ke - D;
+    }
+}
+
+// Decoding constants of a tile copied into vector registers: they are read
+// by every key of the emission loop, and scalar registers are scarce there.
+__device__ __forceinline__ uint32_t vreg(uint32_t x)
+{
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+struct DecV {
+    uint32_t dv, r0, c0, b, sh, msk;
+    double rcp;
+};
+
+__device__ __forceinline__ DecV dec_vregs(const Decoder &d)
+{
+    DecV v;
+    v.dv = vreg(d.dv); v.r0 = vreg(d.r0); v.c0 = vreg(d.c0); v.b = vreg(d.b);
+    v.sh = vreg(d.sh); v.msk = vreg(d.dv - 1);
+    const uint64_t rb = (uint64_t)__double_as_longlong(d.rcp);
+    v.rcp = __longlong_as_double((long long)(((uint64_t)vreg((uint32_t)(rb >> 32)) << 32) | vreg((uint32_t)rb)));
+    return v;
+}
+
+// Directed (TYPE 0) or rectangle (TYPE 1) slot with a 32-bit dividend:
+// quotient by shift or by the binary64 reciprocal estimate, corrected once
+// without branches.
+template <int TYPE, bool POW2>
+__device__ __forceinline__ uint2 dec_narrow(const DecV &d, uint32_t x)
+{
+    const uint32_t y = d.c0 + x;
+    uint32_t q, r;
+    if (POW2) {
+        q = y >> d.sh;
+        r = y & d.msk;
+    } else {
+        q = (uint32_t)((double)y * d.rcp);
+        int32_t rr = (int32_t)(y - q * d.dv);
+        const bool neg = rr < 0;
+        q -= neg ? 1u : 0u;
+        rr += neg ? (int32_t)d.dv : 0;
+        const bool big = (uint32_t)rr >= d.dv;
+        q += big ? 1u : 0u;
+        rr -= big ? (int32_t)d.dv : 0;
+        r = (uint32_t)rr;
+    }
+    const uint32_t u = d.r0 + q;
+    return TYPE == 0 ? make_uint2(u, r + (r >= u ? 1u : 0u)) : make_uint2(u, d.b + r);
+}
+
+// Sorted keys s[0..n) out as edges o0 .. o0 + n - 1, four keys per lane per
+// round (lane-strided, so each store instruction covers 512 contiguous bytes).
+template <int TYPE, bool POW2>
+__device__ __forceinline__ void emit_narrow(const TileCtx &t, const uint32_t *s, uint32_t n)
+{
+    const DecV d = dec_vregs(t.dec);
+    uint2 *out = reinterpret_cast<uint2 *>(t.edges) + t.o0;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t nfull = n & ~255u;
+    for (uint32_t b = 0; b < nfull; b += 256) {
+        uint32_t x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = s[b + lane + 64 * i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[b + lane + 64 * i] = dec_narrow<TYPE, POW2>(d, x[i]);
+    }
+    if (nfull < n) {
+        uint32_t x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t p = nfull + lane + 64 * i;
+            x[i] = p < n ? s[p] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t p = nfull + lane + 64 * i;
+            if (p < n) out[p] = dec_narrow<TYPE, POW2>(d, x[i]);
+        }
+    }
+}
+
+__device__ __forceinline__ void emit_tile(const TileCtx &t, const uint32_t *s, uint32_t n)
+{
+    const Decoder &d = t.dec;
+    if (d.type == 2 || d.wide) emit_sorted(t, s, n);
+    else if (d.type == 0) {
+        if (d.pow2) emit_narrow<0, true>(t, s, n); else emit_narrow<0, false>(t, s, n);
+    } else {
+        if (d.pow2) emit_narrow<1, true>(t, s, n); else emit_narrow<1, false>(t, s, n);
+    }
+}
+
+// Blocked tile range of workgroup blockIdx.x among gridDim.x.
+__device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t1)
+{
+    const uint64_t W = gridDim.x;
+    const uint64_t per = (T + W - 1) / W;
+    t0 = (uint64_t)blockIdx.x * per;
+    t1 = t0 + per < T ? t0 + per : T;
+}
+
+__global__ __launch_bounds__(64) void tile_kernel(Job job)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t s_key[kFastDraws + 8];
+    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords + 4];   // counters, total
+    if (ld_uni(job.status + 1)) return;
+    const uint64_t T = ld_uni(job.status + 2);
+    uint64_t t0, t1;
+    tile_range(T, t0, t1);
+    if (t0 >= t1) return;
+    const uint32_t lim = job.leaf_cap < kFastDraws ? job.leaf_cap : kFastDraws;
+    TileWalk w;
+    w.have = false;
+    w.prev_tl = 0;
+    uint64_t o_next = ld_uni(job.tile_off + t0);
+    for (uint64_t t = t0; t < t1; ++t) {
+        const uint64_t o0 = o_next;
+        o_next = ld_uni(job.tile_off + t + 1);
+        const uint64_t k = o_next - o0;
+        if (k == 0) continue;
+        w.locate(job, t);
+        w.tile(t);
+        TileCtx &tc = w.tc;
+        tc.o0 = o0;
+        tc.edges = job.edges;
+        const bool comp = 2 * k > tc.S;
+        const uint64_t ke = comp ? tc.S - k : k;
+        if (ke == 0) {
+            emit_complement(tc, s_key, 0, 0, tc.S, 0);
+        } else if (ke <= lim && fast_set(tc, s_key, s_cnt, (uint32_t)ke, lim)) {
+            if (!comp) emit_tile(tc, s_key, (uint32_t)ke);
+            else emit_complement(tc, s_key, (uint32_t)ke, 0, tc.S, 0);
+        } else if (threadIdx.x == 0) {
+            const uint64_t q = atomicAdd((unsigned long long *)(job.status + 4), 1ull);
+            job.queue[q] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Tiles the fast kernel queued: one wave per queued tile, general base case.
+template <int CAP>
+__global__ __launch_bounds__(64) void queue_kernel(Job job)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t s_bkt[CAP + 8];
+    __shared__ __attribute__((aligned(16))) uint32_t s_hist[CAP + 8];
+    if (ld_uni(job.status + 1)) return;
+    const uint64_t nq = ld_uni(job.status + 4);
+    const uint32_t cap = job.leaf_cap < CAP ? job.leaf_cap : CAP;
+    for (uint64_t i = blockIdx.x; i < nq; i += gridDim.x) {
+        const uint64_t t = ld_uni(job.queue + i);
+        const uint64_t o0 = ld_uni(job.tile_off + t);
+        const uint64_t k = ld_uni(job.tile_off + t + 1) - o0;
+        TileWalk w;
+        w.have = false;
+        w.prev_tl = 0;
+        w.locate(job, t);
+        w.tile(t);
+        TileCtx &tc = w.tc;
+        tc.o0 = o0;
+        tc.edges = job.edges;
+        leaf_sample<CAP>(tc, s_bkt, s_hist, k, cap);
+        __syncthreads();
+    }
+}
+
+}  // namespace kg
