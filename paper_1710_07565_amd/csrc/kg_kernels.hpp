@@ -636,6 +636,25 @@ __device__ __forceinline__ void win_sort(uint32_t *v)
     }
 }
 
+// Merge of two ascending runs v[0..4) and v[4..8): the second run reversed
+// makes the sequence bitonic, and three compare-exchange stages sort it.
+__device__ __forceinline__ void win_merge8(uint32_t *v)
+{
+    uint32_t t = v[4]; v[4] = v[7]; v[7] = t;
+    t = v[5]; v[5] = v[6]; v[6] = t;
+#pragma unroll
+    for (int j = 4; j > 0; j >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if ((i & j) == 0) {
+                const uint32_t a = v[i], b = v[i + j];
+                v[i] = a < b ? a : b;
+                v[i + j] = a < b ? b : a;
+            }
+        }
+    }
+}
+
 // Two window passes over s[0..V) with windows of 8 keys, R (1 or 2)
 // consecutive windows per lane (s padded with ~0 up to 512 R + 4): lane L
 // sorts windows [8 (R L + r), +8), then the windows shifted by 4.  The result
@@ -667,7 +686,7 @@ __device__ __forceinline__ uint32_t window_passes(uint32_t *s, uint32_t V, uint3
         if (r < R) {
             const uint32_t p0 = 8 * (R * lane + r) + 4;
             win_load<8>(s, p0, v);
-            win_sort<8>(v);
+            win_merge8(v);          // both halves come sorted from the first pass
             win_store<8>(s, p0, v);
 #pragma unroll
             for (int i = 0; i < 7; ++i)

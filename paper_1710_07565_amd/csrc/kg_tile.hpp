@@ -140,6 +140,131 @@ struct TileWalk {
     }
 };
 
+// Sorting and merging networks for the window passes (comparator pairs,
+// checked exhaustively by the 0-1 principle): an optimal 8-key sort, the
+// merge-exchange sort of 10 keys, and the odd-even merges of two sorted
+// halves of 4 or 5 keys.
+__device__ __forceinline__ void cx(uint32_t *v, int a, int b)
+{
+    const uint32_t x = v[a], y = v[b];
+    v[a] = x < y ? x : y;
+    v[b] = x < y ? y : x;
+}
+
+template <int W> __device__ __forceinline__ void net_sort(uint32_t *v);
+template <int W> __device__ __forceinline__ void net_merge(uint32_t *v);
+
+template <> __device__ __forceinline__ void net_sort<8>(uint32_t *v)
+{
+    constexpr uint8_t n[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                                  {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+    for (int c = 0; c < 19; ++c) cx(v, n[c][0], n[c][1]);
+}
+template <> __device__ __forceinline__ void net_merge<8>(uint32_t *v)
+{
+    constexpr uint8_t n[9][2] = {{0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+    for (int c = 0; c < 9; ++c) cx(v, n[c][0], n[c][1]);
+}
+template <> __device__ __forceinline__ void net_sort<10>(uint32_t *v)
+{
+    constexpr uint8_t n[31][2] = {{0, 8}, {1, 9}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {4, 8}, {5, 9}, {0, 2}, {1, 3},
+                                  {4, 6}, {5, 7}, {2, 8}, {3, 9}, {2, 4}, {3, 5}, {6, 8}, {7, 9}, {0, 1}, {2, 3},
+                                  {4, 5}, {6, 7}, {8, 9}, {1, 8}, {1, 4}, {3, 6}, {5, 8}, {1, 2}, {3, 4}, {5, 6},
+                                  {7, 8}};
+#pragma unroll
+    for (int c = 0; c < 31; ++c) cx(v, n[c][0], n[c][1]);
+}
+template <> __device__ __forceinline__ void net_merge<10>(uint32_t *v)
+{
+    constexpr uint8_t n[15][2] = {{0, 8}, {1, 9}, {1, 5}, {2, 6}, {3, 7}, {4, 8}, {0, 2}, {4, 6}, {3, 5}, {7, 9},
+                                  {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9}};
+#pragma unroll
+    for (int c = 0; c < 15; ++c) cx(v, n[c][0], n[c][1]);
+}
+
+template <int W>
+__device__ __forceinline__ void wload(const uint32_t *s, uint32_t p0, uint32_t *v)
+{
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[i] = s[p0 + i];
+}
+template <int W>
+__device__ __forceinline__ void wstore(uint32_t *s, uint32_t p0, const uint32_t *v)
+{
+#pragma unroll
+    for (int i = 0; i < W; ++i) s[p0 + i] = v[i];
+}
+
+// Window passes over s[0..span), span = 64 W R + W/2, positions V.. padded
+// with ~0 (no key equals ~0).  Lane L sorts windows [W (R L + r), +W), then
+// merges the windows shifted by W/2 (whose halves are sorted by the first
+// pass).  The result is sorted unless a bucket of more than W/2 + 1 keys
+// lies across a window boundary; every adjacent pair of [0, span) is
+// compared once from registers.  Returns the mask of lanes that saw a pair
+// out of order and adds the equal pairs among the first V positions to dups.
+template <int W, int R>
+__device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &dups)
+{
+    constexpr int H = W / 2;
+    const uint32_t lane = threadIdx.x;
+    uint32_t v[W], head[H];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t p0 = W * (R * lane + r);
+        wload<W>(s, p0, v);
+        net_sort<W>(v);
+        wstore<W>(s, p0, v);
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) head[i] = v[i];
+        }
+    }
+    __syncthreads();
+    uint64_t bad = 0;
+    uint32_t eq = 0, first = 0, last = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t p0 = W * (R * lane + r) + H;
+        wload<W>(s, p0, v);
+        net_merge<W>(v);
+        wstore<W>(s, p0, v);
+#pragma unroll
+        for (int i = 0; i + 1 < W; ++i) {
+            bad |= __ballot(v[i] > v[i + 1]);
+            eq += __popcll(__ballot(v[i] == v[i + 1]));
+        }
+        if (r == 0) {
+            first = v[0];
+        } else {
+            bad |= __ballot(last > v[0]);
+            eq += __popcll(__ballot(last == v[0]));
+        }
+        last = v[W - 1];
+    }
+    // lane boundaries, and the head [0, H) of lane 0's first window
+    const uint32_t nxt = __shfl_down(first, 1, 64);
+    const bool inner = lane < 63;
+    bad |= __ballot(inner && last > nxt);
+    eq += __popcll(__ballot(inner && last == nxt));
+    uint32_t hb = 0, he = 0;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const uint32_t y = i + 1 < H ? head[i + 1] : first;
+            hb |= head[i] > y;
+            he += head[i] == y;
+        }
+    }
+    bad |= __ballot(hb != 0);
+    eq += __builtin_amdgcn_readfirstlane(he);
+    // pairs inside the padding [V, span) are all equal; the pair (V - 1, V) is not
+    constexpr uint32_t span = 64 * W * R + H;
+    dups = eq - (span - 1 - V);
+    return bad;
+}
+
 // Base case of the common tiles.  Pass 1 (one Philox block per lane and
 // trip; lane L computes blocks L + 64 e, i.e. draws 256 e + 4 L + q) counts
 // every valid draw in its bucket -- the top min(10, bits) bits of the key,
@@ -152,6 +277,7 @@ struct TileWalk {
 // Leaves the sorted set in s[0..ke) and returns true, or returns false once
 // J would exceed lim.
 constexpr uint32_t kBucketWords = 512;   // 1024 16-bit counters
+constexpr uint32_t kDump = kFastDraws + 8;   // s[kDump + lane]: writes of ~0 entries
 
 __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t *cnt, uint32_t ke, uint32_t lim)
 {
@@ -166,6 +292,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         cw[1] = make_uint4(0, 0, 0, 0);
         __syncthreads();
         const uint32_t nit = uni((J + 255) >> 8);
+        uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
 #pragma unroll 1
         for (uint32_t e = 0; e < nit; ++e) {
             const uint32_t blk = lane + 64u * e;
@@ -173,17 +300,17 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const bool ok = 4 * blk + q < J && (t.full || v[q] < S32);
-                if (ok) {
-                    const uint32_t b = v[q] >> shift;
-                    atomicAdd(&cnt[b >> 1], 1u << ((b & 1) << 4));
-                } else {
-                    v[q] = kNone;
-                }
+                // branch-free: a draw past J or rejected adds 0 and is staged as ~0
+                const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
+                coll |= __ballot(ok & (v[q] == kNone));
+                const uint32_t b = v[q] >> shift;
+                atomicAdd(&cnt[b >> 1], ok ? 1u << ((b & 1) << 4) : 0u);
+                v[q] = ok ? v[q] : kNone;
             }
             *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
         }
         __syncthreads();
+        if (coll) return false;
         {
             const uint4 c0 = cw[0], c1 = cw[1];
             uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
@@ -205,7 +332,8 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         }
         __syncthreads();
         {
-            // every staged draw is loaded before the first one is placed
+            // every staged draw is loaded before the first one is placed;
+            // a ~0 entry adds 0 and is written to this lane's dump word
             uint32_t x[16];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -215,11 +343,23 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             }
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if (x[i] != kNone) {
-                    const uint32_t b = x[i] >> shift, h = (b & 1) << 4;
-                    const uint32_t pos = (atomicAdd(&cnt[b >> 1], 1u << h) >> h) & 0xFFFFu;
-                    s[pos] = x[i];
+            for (int e = 0; e < 4; ++e) {
+                if ((uint32_t)e < nit) {
+                    uint32_t old[4], h[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t xv = x[4 * e + q];
+                        const bool ok = xv != kNone;
+                        const uint32_t b = ok ? xv >> shift : 0u;   // b < 1024
+                        h[q] = (b & 1) << 4;
+                        old[q] = atomicAdd(&cnt[b >> 1], ok ? 1u << h[q] : 0u);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t xv = x[4 * e + q];
+                        const uint32_t pos = xv != kNone ? (old[q] >> h[q]) & 0xFFFFu : kDump + lane;
+                        s[pos] = xv;
+                    }
                 }
             }
         }
@@ -227,18 +367,21 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         const uint32_t V = uni(cnt[kBucketWords]);
         uint32_t ndup = 0;
         {
-            const uint32_t R = V <= 512 ? 1 : 2;
-            const uint32_t span = 512 * R + 4;
+            // window width and count per lane from V: 8 keys (V <= 512),
+            // 10 keys (V <= 640) or two windows of 8 (V <= 1024)
+            const int mode = V <= 512 ? 0 : V <= 640 ? 1 : 2;
+            const uint32_t span = mode == 0 ? 516 : mode == 1 ? 645 : 1028;
             for (uint32_t p = V + lane; p < span; p += 64) s[p] = kNone;
             for (;;) {
                 __syncthreads();
-                const uint32_t r = window_passes(s, V, R);
-                ndup = r >> 1;
-                if (!__syncthreads_or(r & 1)) break;
+                uint64_t bad;
+                if (mode == 0) bad = windows<8, 1>(s, V, ndup);
+                else if (mode == 1) bad = windows<10, 1>(s, V, ndup);
+                else bad = windows<8, 2>(s, V, ndup);
+                __syncthreads();
+                if (!bad) break;
             }
         }
-        ndup = __builtin_amdgcn_readlane(wave_incl_scan32(ndup), 63);
-        __syncthreads();
         const uint32_t D = V - ndup;
         if (D == ke) {
             if (ndup) {
@@ -367,7 +510,7 @@ __device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t
 
 __global__ __launch_bounds__(64) void tile_kernel(Job job)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t s_key[kFastDraws + 8];
+    __shared__ __attribute__((aligned(16))) uint32_t s_key[kDump + 64];
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords + 4];   // counters, total
     if (ld_uni(job.status + 1)) return;
     const uint64_t T = ld_uni(job.status + 2);

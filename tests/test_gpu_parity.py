@@ -65,6 +65,8 @@ MID = [
     (2**12, 2**16, False, 8), (5000, 10**6, False, 33), (777, 100000, False, 1), (777, 300000, False, 5),
     (2**14, 2**21, True, 1), (123456, 10**6, True, 1000), (2**17, 2**20, False, 256), (600, 179700, False, 2),
     (90, 8000, True, 90), (10**5, 3 * 10**6, False, 100),
+    # tiles of 2^32 slots (keys use all 32 bits)
+    (2**26, 2**20, False, 256), (2**26, 2**21, True, 64),
 ]
 
 
