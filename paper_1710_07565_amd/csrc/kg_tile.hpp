@@ -311,6 +311,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         }
         __syncthreads();
         if (coll) return false;
+        uint32_t V;             // valid draws
         {
             const uint4 c0 = cw[0], c1 = cw[1];
             uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
@@ -328,7 +329,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             }
             cw[0] = make_uint4(w[0], w[1], w[2], w[3]);
             cw[1] = make_uint4(w[4], w[5], w[6], w[7]);
-            if (lane == 63) cnt[kBucketWords] = incl;
+            V = __builtin_amdgcn_readlane(incl, 63);
         }
         __syncthreads();
         {
@@ -364,7 +365,6 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             }
         }
         __syncthreads();
-        const uint32_t V = uni(cnt[kBucketWords]);
         uint32_t ndup = 0;
         {
             // window width and count per lane from V: 8 keys (V <= 512),
@@ -511,39 +511,92 @@ __device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t
 __global__ __launch_bounds__(64) void tile_kernel(Job job)
 {
     __shared__ __attribute__((aligned(16))) uint32_t s_key[kDump + 64];
-    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords + 4];   // counters, total
+    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords + 4];   // counters
     if (ld_uni(job.status + 1)) return;
     const uint64_t T = ld_uni(job.status + 2);
-    uint64_t t0, t1;
-    tile_range(T, t0, t1);
-    if (t0 >= t1) return;
+    uint64_t t, t1;
+    tile_range(T, t, t1);
+    if (t >= t1) return;
     const uint32_t lim = job.leaf_cap < kFastDraws ? job.leaf_cap : kFastDraws;
-    TileWalk w;
-    w.have = false;
-    w.prev_tl = 0;
-    uint64_t o_next = ld_uni(job.tile_off + t0);
-    for (uint64_t t = t0; t < t1; ++t) {
-        const uint64_t o0 = o_next;
-        o_next = ld_uni(job.tile_off + t + 1);
-        const uint64_t k = o_next - o0;
-        if (k == 0) continue;
-        w.locate(job, t);
-        w.tile(t);
-        TileCtx &tc = w.tc;
-        tc.o0 = o0;
-        tc.edges = job.edges;
-        const bool comp = 2 * k > tc.S;
-        const uint64_t ke = comp ? tc.S - k : k;
-        if (ke == 0) {
-            emit_complement(tc, s_key, 0, 0, tc.S, 0);
-        } else if (ke <= lim && fast_set(tc, s_key, s_cnt, (uint32_t)ke, lim)) {
-            if (!comp) emit_tile(tc, s_key, (uint32_t)ke);
-            else emit_complement(tc, s_key, (uint32_t)ke, 0, tc.S, 0);
-        } else if (threadIdx.x == 0) {
-            const uint64_t q = atomicAdd((unsigned long long *)(job.status + 4), 1ull);
-            job.queue[q] = t;
+    // chunk of the first tile: last g with tstart[g] <= t
+    uint64_t g;
+    {
+        uint64_t lo = 0, hi = job.G;
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
         }
-        __syncthreads();
+        g = lo;
+    }
+    // tile offsets are read two tiles ahead: they come from HBM (the output
+    // stream evicts them from the caches), so a tile never waits for its own
+    uint64_t o_next = ld_uni(job.tile_off + t);
+    uint64_t o_pre = ld_uni(job.tile_off + t + 1);
+    TileWalk w;
+    TileCtx &tc = w.tc;
+    Decoder &d = tc.dec;
+    tc.edges = job.edges;
+    for (;;) {
+        // chunk constants, then the decoder at the wave's first tile of the chunk
+        w.enter(job, g);
+        const uint64_t tend = w.gend < t1 ? w.gend : t1;
+        const uint32_t s = w.s;
+        const uint64_t full_S = 1ull << s;
+        uint64_t lstart = (t - w.gstart) << s;
+        if (d.type != 2) {
+            const uint64_t q = lstart / d.dv;
+            d.c0 = uni((uint32_t)(lstart - q * d.dv));
+            d.r0 = uni(w.row0 + (uint32_t)q);
+        }
+        const uint32_t qs32 = (uint32_t)w.qs;
+        for (; t < tend; ++t) {
+            const uint64_t o0 = o_next;
+            o_next = o_pre;
+            if (t + 2 <= T) o_pre = ld_uni(job.tile_off + t + 2);
+            const uint64_t k = o_next - o0;
+            if (k != 0) {
+                // slots of the tile: 2^s except for the chunk's last tile
+                if (t + 1 < w.gend) {
+                    tc.S = full_S;
+                    tc.bits = s;
+                    tc.mask = s >= 32 ? 0xFFFFFFFFu : (1u << s) - 1;
+                    tc.full = 1;
+                } else {
+                    tc.S = uni64(w.N - lstart);
+                    tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
+                    tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
+                    tc.full = uni(tc.S == (1ull << tc.bits));
+                }
+                tc.st.b = uni((uint32_t)(t - w.gstart));
+                d.lbase = lstart;
+                d.wide = s == 32 ? uni((uint64_t)d.c0 + tc.S > (1ull << 32)) : 0u;
+                tc.o0 = o0;
+                const bool comp = 2 * k > tc.S;
+                const uint64_t ke = comp ? tc.S - k : k;
+                if (ke == 0) {
+                    emit_complement(tc, s_key, 0, 0, tc.S, 0);
+                } else if (ke <= lim && fast_set(tc, s_key, s_cnt, (uint32_t)ke, lim)) {
+                    if (!comp) emit_tile(tc, s_key, (uint32_t)ke);
+                    else emit_complement(tc, s_key, (uint32_t)ke, 0, tc.S, 0);
+                } else if (threadIdx.x == 0) {
+                    const uint64_t q = atomicAdd((unsigned long long *)(job.status + 4), 1ull);
+                    job.queue[q] = t;
+                }
+                __syncthreads();
+            }
+            // next tile of the chunk: 2^s = qs dv + rs slots further
+            lstart += full_S;
+            if (d.type != 2) {
+                uint32_t c0 = d.c0 + w.rs, r0 = d.r0 + qs32;
+                if (c0 >= d.dv) { c0 -= d.dv; ++r0; }
+                d.c0 = c0;
+                d.r0 = r0;
+            }
+        }
+        if (t >= t1) break;
+        // next chunk that has tiles
+        ++g;
+        while (ld_uni(job.tstart + g + 1) <= t) ++g;
     }
 }
 
