@@ -42,16 +42,20 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kg_device.hpp", "kg_kernels.hpp", "kg_lib.hip"):
+    for f in ("kg_device.hpp", "kg_kernels.hpp", "kg_tile.hpp", "kg_lib.hip"):
         with open(os.path.join(ROOT, "paper_1710_07565_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "tile_kernel_traffic.json")
+ROOFLINE_KERNEL = "tile_kernel"
+
+
 def traffic_for(workload):
-    """HBM bytes per sampler launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "sample_kernel_traffic.json")
+    """HBM bytes per tile_kernel launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = TRAFFIC_PATH
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -61,6 +65,50 @@ def traffic_for(workload):
     if not ent or ent.get("kernel_source") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
+
+
+def _pmc_per_dispatch(run_dir, counter):
+    """{(dispatch id, kernel name): summed counter value} from rocprofv3 CSVs."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def write_traffic(workload, fetch_dir, write_dir, copy_gib, commands):
+    """Scale the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of
+    tile_kernel by what the same counters read for the calibration copy
+    (copy_gib GiB read and written) and record the HBM bytes per launch."""
+    res = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = _pmc_per_dispatch(d, ctr)
+        copies = [v for (i, nm), v in per.items() if "copyBuffer" in nm or "copy" in nm.lower()]
+        tiles = [v for (i, nm), v in per.items() if ROOFLINE_KERNEL in nm]
+        if not copies or not tiles:
+            raise SystemExit("no %s records for the copy kernel and %s in %s" % (ctr, ROOFLINE_KERNEL, d))
+        scale = copy_gib * 2**20 / max(copies)          # KiB expected / KiB counted
+        res[ctr] = {"raw_kib_per_launch": sum(tiles) / len(tiles), "launches": len(tiles),
+                    "copy_kib": max(copies), "scale": scale}
+    total = sum(v["raw_kib_per_launch"] * v["scale"] * 1024 for v in res.values())
+    try:
+        with open(TRAFFIC_PATH) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    rec[workload] = {"kernel": ROOFLINE_KERNEL, "kernel_source": kernel_source_hash(), "bytes_per_launch": total,
+                     "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"], "calibration_copy_gib": copy_gib,
+                     "commands": commands}
+    with open(TRAFFIC_PATH, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    log("traffic for %s: %.4g bytes per launch" % (workload, total))
 
 
 def cpu_baseline(desc, seconds):
@@ -137,7 +185,7 @@ def run_plain(args, desc):
             edges_per_step.append(kg.gnp_count(n, p, directed, seeds[i % len(seeds)], P, workspace=ws))
     torch.cuda.synchronize()
     kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
-    for k in range(4):
+    for k in range(5):
         kg.kernel_time_read(k)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -150,7 +198,8 @@ def run_plain(args, desc):
     wall = time.perf_counter() - t0
     kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
     ms = e0.elapsed_time(e1)
-    kt = {nm: kg.kernel_time_read(k) for k, nm in ((0, "count"), (1, "scan"), (2, "plan"), (3, "sample"))}
+    kt = {nm: kg.kernel_time_read(k) for k, nm in ((0, "count"), (1, "scan"), (2, "plan"), (3, "sample"),
+                                                   (4, "queue"))}
     if model == 1:
         got = int(total.view(torch.int64).item())
         assert got == edges_per_step[(args.steps - 1) % len(edges_per_step)], "edge total mismatch"
@@ -174,7 +223,7 @@ def run_plain(args, desc):
         "pct_hbm_write_bw": 100.0 * BYTES_PER_EDGE * E / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "sample_kernel", "avg_launch_ms": samp_avg,
+                     "kernel": ROOFLINE_KERNEL, "avg_launch_ms": samp_avg,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "wall_s_timed": wall,
@@ -287,7 +336,7 @@ def run_batch(args):
         "roofline": {"bound": "hbm", "achieved": BYTES_PER_EDGE * E * args.steps / (samp_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": BYTES_PER_EDGE * E * args.steps / (samp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "kernel": "sample_kernel", "avg_launch_ms": samp_ms / max(samp_n, 1)},
+                     "traffic": None, "kernel": ROOFLINE_KERNEL, "avg_launch_ms": samp_ms / max(samp_n, 1)},
         "batching": {"sample_instances": len(sample), "sample_edges": E_sample,
                      "one_call_each_edges_per_s": E_sample / (ms_single * 1e-3),
                      "one_kg_batch_edges_per_s": E_sample / (ms_batch_sample * 1e-3)},
@@ -342,7 +391,19 @@ def main():
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no run: read rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of a profiled "
+                         "run of this workload (with --calibrate-copy-gib) and record the tile_kernel HBM traffic "
+                         "in profiles/tile_kernel_traffic.json")
+    ap.add_argument("--traffic-command", action="append", default=[],
+                    help="the profiling commands, recorded with the traffic figure")
     args = ap.parse_args()
+    if args.traffic_from:
+        if args.calibrate_copy_gib <= 0:
+            raise SystemExit("--traffic-from needs --calibrate-copy-gib (the size of the profiled calibration copy)")
+        write_traffic(args.workload, args.traffic_from[0], args.traffic_from[1], args.calibrate_copy_gib,
+                      args.traffic_command)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the generator needs no communication and this build "
               "measures a single MI355X (got --gpus %d)" % args.gpus, file=sys.stderr)

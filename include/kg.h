@@ -126,7 +126,13 @@ int64_t kg_get_option(int option);
  * the launch stream.  kg_kernel_time_read waits for the recorded events,
  * returns the summed milliseconds and the number of launches, and forgets
  * them.  Host only; synchronises with the recorded events. */
-enum { KG_KERNEL_COUNT = 0, KG_KERNEL_SCAN = 1, KG_KERNEL_PLAN = 2, KG_KERNEL_SAMPLE = 3 };
+enum {
+    KG_KERNEL_COUNT = 0,   /* per-chunk counts */
+    KG_KERNEL_SCAN = 1,    /* offsets */
+    KG_KERNEL_PLAN = 2,    /* tile plan */
+    KG_KERNEL_SAMPLE = 3,  /* common-case tile sampler */
+    KG_KERNEL_QUEUE = 4    /* general base case for the tiles the sampler queued */
+};
 kg_status kg_kernel_time_read(int kernel, double *ms_total, uint64_t *launches);
 
 /* Element-wise evaluation of the device building blocks, for checking them

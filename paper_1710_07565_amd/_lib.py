@@ -14,7 +14,7 @@ EXPORTS = ["kg_spec_version", "kg_strerror", "kg_workspace_bytes", "kg_gnm", "kg
            "kg_chunk_counts", "kg_batch", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_eval",
            "kg_kernel_time_read"]
 KG_OPT_TIME_KERNELS = 4
-KG_KERNEL_COUNT, KG_KERNEL_SCAN, KG_KERNEL_PLAN, KG_KERNEL_SAMPLE = 0, 1, 2, 3
+KG_KERNEL_COUNT, KG_KERNEL_SCAN, KG_KERNEL_PLAN, KG_KERNEL_SAMPLE, KG_KERNEL_QUEUE = 0, 1, 2, 3, 4
 KG_EVAL_PHILOX, KG_EVAL_LOG, KG_EVAL_LOG1P, KG_EVAL_LNF_DIFF, KG_EVAL_HYP, KG_EVAL_BIN, KG_EVAL_SQRT_DIV = range(1, 8)
 
 

@@ -34,7 +34,7 @@ int64_t g_time_kernels = 0;
 
 // Event pairs recorded around kernel launches while timing is on.
 std::mutex g_time_mu;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[4];
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[5];
 
 struct KernelTimer {
     int id;
@@ -270,6 +270,9 @@ kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
     {
         KernelTimer tm(KG_KERNEL_SAMPLE, s);
         hipLaunchKernelGGL(tile_kernel, dim3((uint32_t)sgrid), dim3(64), 0, s, job);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_QUEUE, s);
         hipLaunchKernelGGL(queue_kernel<kCapMax>, dim3((uint32_t)qgrid), dim3(64), 0, s, job);
     }
     return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
@@ -445,7 +448,7 @@ kg_status kg_set_option(int option, int64_t value)
 
 kg_status kg_kernel_time_read(int kernel, double *ms_total, uint64_t *launches)
 {
-    if (kernel < 0 || kernel > 3 || !ms_total || !launches) return KG_EINVAL;
+    if (kernel < 0 || kernel > 4 || !ms_total || !launches) return KG_EINVAL;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     {
         std::lock_guard<std::mutex> lk(g_time_mu);
