@@ -21,7 +21,7 @@ namespace kg {
 // ---------------------------------------------------------------------------
 // Constants of the method
 // ---------------------------------------------------------------------------
-constexpr uint32_t kLambda = 512;       // expected samples per tile (sampling threshold)
+constexpr uint32_t kLambda = 362;       // tiles hold [362, 724) samples in expectation (~512/sqrt 2 .. 512 sqrt 2)
 constexpr uint32_t kUnitTiles = 64;     // most tiles of one planner unit (one lane expands it)
 constexpr uint32_t kLnfTab = 1024;      // ln k! tabulated for k <= kLnfTab
 
@@ -53,10 +53,45 @@ __host__ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t
     return U4{c0, c1, c2, c3};
 }
 
+// The same rounds for a key held in scalar registers (the same key in every
+// lane of the wave): the three-way xor of a round is one v_bitop3_b32 (a
+// three-input bitwise function given by its truth table; 0x96 is a ^ b ^ c)
+// with the round key as its scalar operand.
+__device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+__device__ __forceinline__ U4 philox_uniform_key(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3_sk((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_sk((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
 // A random stream: Philox keyed by the seed, counter (block, a, b, tag).
 struct Stream {
     uint32_t k0, k1, a, b, tag;
     __device__ __forceinline__ U4 block(uint32_t j) const { return philox(j, a, b, tag, k0, k1); }
+    // only when k0, k1 are wave-uniform (scalar registers)
+    __device__ __forceinline__ U4 block_uniform_key(uint32_t j) const
+    {
+        return philox_uniform_key(j, a, b, tag, k0, k1);
+    }
 };
 
 __device__ __forceinline__ Stream make_stream(uint64_t seed, uint32_t a, uint32_t b, uint32_t tag)

@@ -296,7 +296,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
 #pragma unroll 1
         for (uint32_t e = 0; e < nit; ++e) {
             const uint32_t blk = lane + 64u * e;
-            const U4 w = t.st.block(blk);
+            const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
             uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {

@@ -93,10 +93,11 @@ def test_generation_calls_reject_bad_arguments_without_a_device(L):
 
 
 def test_oracle_tile_exponent_is_minimal(kgref):
-    """The tile exponent is the smallest s in [9, 32] with 2^s m >= 512 N."""
+    """The tile exponent is the smallest s in [9, 32] with 2^s m >= 362 N
+    (tiles hold 362..724 samples in expectation)."""
     for n, m in [(2**16, 2**20), (2**10, 2**19), (50, 1225), (2**20, 5)]:
         I = kgref.inst(n, m=m, directed=True, seed=1, chunks=1)
         s = kgref.tile_exponent(I)
         N = n * (n - 1)
-        assert (m << s) >= 512 * N or s == 32
-        assert s == 9 or (m << (s - 1)) < 512 * N
+        assert (m << s) >= 362 * N or s == 32
+        assert s == 9 or (m << (s - 1)) < 362 * N
