@@ -144,8 +144,19 @@ def cpu_baseline(desc, seconds):
         if t_gen >= seconds:
             break
     t = t_gen + t_counts * done / C
+    # one thread, on a short stretch of the same chunk order
+    e1, t1 = 0, 0.0
+    for c0 in order[:8]:
+        c1 = min(C, c0 + 32)
+        t0 = time.perf_counter()
+        r = kgref.generate_chunks(I, counts, c0, c1, out=buf, threads=1)
+        t1 += time.perf_counter() - t0
+        e1 += len(r)
+        if t1 >= seconds / 5:
+            break
     return {"value": edges / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d chunks (%d edges, %.1f s), seed 1" % (done, C, edges, t)}
+            "sample": "%d of %d chunks (%d edges, %.1f s), seed 1" % (done, C, edges, t),
+            "one_thread": {"value": e1 / t1, "unit": "edges/s", "edges": e1, "seconds": t1}}
 
 
 def run_plain(args, desc):
@@ -187,17 +198,18 @@ def run_plain(args, desc):
     kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
     for k in range(5):
         kg.kernel_time_read(k)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
+    ev[0].record(stream)
     for i in range(args.steps):
         step(i)
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
-    ms = e0.elapsed_time(e1)
+    ms = ev[0].elapsed_time(ev[-1])
+    per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
     kt = {nm: kg.kernel_time_read(k) for k, nm in ((0, "count"), (1, "scan"), (2, "plan"), (3, "sample"),
                                                    (4, "queue"))}
     if model == 1:
@@ -216,6 +228,7 @@ def run_plain(args, desc):
         "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": per_step[len(per_step) // 2], "ms_per_step_min": per_step[0],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": desc[0], "n": n, "m": m, "p": p, "directed": directed, "P": P,
@@ -359,6 +372,22 @@ def run_serve(args):
     reqs, st = serve.run_stream(srv, stream, warmup_s=args.serve_warmup,
                                 progress=lambda t, i, q, f: log("  t=%.0fs arrived=%d queued=%d inflight=%d"
                                                                 % (t, i, q, f)))
+    sweep = []
+    if args.sweep:
+        # saturation: double the rate until the p99 latency diverges
+        rate = args.rate * 2
+        while rate <= args.rate * 64:
+            srv2 = serve.Server(budget_bytes=int(args.budget_gb * 1e9), streams=args.streams,
+                                max_batch=args.max_batch)
+            st2 = serve.run_stream(srv2, workloads.request_stream(rate_per_s=rate, duration_s=args.sweep_seconds,
+                                                                  base_seed=2, seed_fn=kg.instance_seed),
+                                   warmup_s=min(2.0, args.sweep_seconds / 4))[1]
+            sweep.append({"rate_per_s": rate, "edges_per_s": st2["edges_per_s"], "p50_s": st2["p50_s"],
+                          "p99_s": st2["p99_s"], "requests": st2["requests"], "span_s": st2["span_s"]})
+            log("  sweep %.0f req/s: %.3g edges/s, p99 %.3f s" % (rate, st2["edges_per_s"], st2["p99_s"] or -1))
+            if st2["p99_s"] is None or st2["p99_s"] > 1.0 or st2["span_s"] > 1.5 * args.sweep_seconds:
+                break
+            rate *= 2
     return {
         "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
         "value": st["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -368,6 +397,8 @@ def run_serve(args):
                                "[2^12,2^24], mean degree uniform [4,32], %.0f GB budget"
                                % (args.rate, args.duration, args.budget_gb)},
         "served": st,
+        "saturation_sweep": sweep,
+        "peak_served_edges_per_s": max([st["edges_per_s"]] + [x["edges_per_s"] for x in sweep]),
     }
 
 
@@ -388,6 +419,8 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=256)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--sweep", action="store_true", help="serve mode: also sweep the arrival rate up to saturation")
+    ap.add_argument("--sweep-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a kernel of known traffic for "
                          "scaling hardware byte counters)")

@@ -108,38 +108,78 @@ __global__ __launch_bounds__(64) void count_kernel(Job job)
 }
 
 // ---------------------------------------------------------------------------
-// scan: one workgroup of 1024 lanes, exclusive scans of the three per-chunk
-// arrays (each lane owns a contiguous segment), then the totals.
+// scan: one workgroup of 1024 lanes walks the three per-chunk arrays in
+// rounds of 4096 entries (four consecutive entries per lane, coalesced):
+// per-lane sums, wave scans, a scan of the 16 wave totals, a running carry.
+// The next round's entries are loaded before the current round is scanned.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v)
+{
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void scan_kernel(Job job)
 {
-    __shared__ uint64_t s_part[3][1024];
-    const uint32_t t = threadIdx.x;
+    __shared__ uint64_t s_wave[3][16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint64_t G = job.G;
-    const uint64_t seg = (G + 1023) / 1024;
-    const uint64_t b0 = t * seg < G ? t * seg : G;
-    const uint64_t b1 = b0 + seg < G ? b0 + seg : G;
-    uint64_t sc = 0, st = 0, su = 0;
-    for (uint64_t g = b0; g < b1; ++g) { sc += job.off[g]; st += job.tstart[g]; su += job.ustart[g]; }
-    s_part[0][t] = sc; s_part[1][t] = st; s_part[2][t] = su;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 partial sums
-    for (uint32_t d = 1; d < 1024; d <<= 1) {
-        uint64_t a0 = 0, a1 = 0, a2 = 0;
-        if (t >= d) { a0 = s_part[0][t - d]; a1 = s_part[1][t - d]; a2 = s_part[2][t - d]; }
+    uint64_t *arr[3] = {job.off, job.tstart, job.ustart};
+    uint64_t carry[3] = {0, 0, 0};
+    uint64_t cur[3][4], nxt[3][4];
+    auto load = [&](uint64_t base, uint64_t (&dst)[3][4]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint64_t g = base + 4 * (uint64_t)t + i;
+                dst[a][i] = g < G ? arr[a][g] : 0;
+            }
+    };
+    load(0, cur);
+    for (uint64_t base = 0; base < G; base += 4096) {
+        if (base + 4096 < G) load(base + 4096, nxt);
+        uint64_t incl[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const uint64_t sum = cur[a][0] + cur[a][1] + cur[a][2] + cur[a][3];
+            incl[a] = wave_incl_scan64(sum);
+            if (lane == 63) s_wave[a][wv] = incl[a];
+            incl[a] -= sum;                       // exclusive within the wave
+        }
         __syncthreads();
-        s_part[0][t] += a0; s_part[1][t] += a1; s_part[2][t] += a2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            uint64_t before = carry[a], total = 0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) {
+                const uint64_t x = s_wave[a][w];
+                if ((uint32_t)w < wv) before += x;
+                total += x;
+            }
+            uint64_t run = before + incl[a];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint64_t g = base + 4 * (uint64_t)t + i;
+                const uint64_t c = cur[a][i];
+                if (g < G) arr[a][g] = run;
+                run += c;
+            }
+            carry[a] += total;
+        }
         __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cur[a][i] = nxt[a][i];
     }
-    uint64_t pc = t ? s_part[0][t - 1] : 0, pt = t ? s_part[1][t - 1] : 0, pu = t ? s_part[2][t - 1] : 0;
-    for (uint64_t g = b0; g < b1; ++g) {
-        const uint64_t c0 = job.off[g], t0 = job.tstart[g], u0 = job.ustart[g];
-        job.off[g] = pc; job.tstart[g] = pt; job.ustart[g] = pu;
-        pc += c0; pt += t0; pu += u0;
-    }
-    __syncthreads();
     if (t == 0) {
-        const uint64_t E = s_part[0][1023], T = s_part[1][1023], U = s_part[2][1023];
+        const uint64_t E = carry[0], T = carry[1], U = carry[2];
         job.off[G] = E; job.tstart[G] = T; job.ustart[G] = U;
         const uint64_t overflow = (E > job.capacity || T > job.tile_cap) ? 1 : 0;
         job.status[0] = E; job.status[1] = overflow; job.status[2] = T; job.status[3] = U;
