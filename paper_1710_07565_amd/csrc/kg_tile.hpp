@@ -15,7 +15,8 @@
 
 namespace kg {
 
-constexpr uint32_t kFastDraws = 1024;   // draws one wave keeps in registers
+constexpr uint32_t kFastDraws = 832;    // draws of one wave's base case (at most 4 Philox blocks per lane)
+constexpr uint32_t kKeyWords = 840;     // LDS key words: >= kFastDraws + 3 and >= the widest window span (838)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // Wave-uniform 64-bit load through the scalar data cache.  Only for data
@@ -141,9 +142,10 @@ struct TileWalk {
 };
 
 // Sorting and merging networks for the window passes (comparator pairs,
-// checked exhaustively by the 0-1 principle): an optimal 8-key sort, the
-// merge-exchange sort of 10 keys, and the odd-even merges of two sorted
-// halves of 4 or 5 keys.
+// checked exhaustively by the 0-1 principle): an optimal 8-key sort,
+// Batcher's merge-exchange sorts of 10, 12 and 13 keys, and merges of two
+// sorted runs (4+4, 5+5, 6+6, 7+6 keys) obtained from those sorts by dropping
+// every comparator the merge does not need.
 __device__ __forceinline__ void cx(uint32_t *v, int a, int b)
 {
     const uint32_t x = v[a], y = v[b];
@@ -182,6 +184,43 @@ template <> __device__ __forceinline__ void net_merge<10>(uint32_t *v)
                                   {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9}};
 #pragma unroll
     for (int c = 0; c < 15; ++c) cx(v, n[c][0], n[c][1]);
+}
+
+template <> __device__ __forceinline__ void net_sort<12>(uint32_t *v)
+{
+    constexpr uint8_t n[41][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {4, 8}, {5, 9},
+                                  {6, 10}, {7, 11}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {8, 10}, {9, 11}, {2, 8},
+                                  {3, 9}, {2, 4}, {3, 5}, {6, 8}, {7, 9}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9},
+                                  {10, 11}, {1, 8}, {3, 10}, {1, 4}, {3, 6}, {5, 8}, {7, 10}, {1, 2}, {3, 4},
+                                  {5, 6}, {7, 8}, {9, 10}};
+#pragma unroll
+    for (int c = 0; c < 41; ++c) cx(v, n[c][0], n[c][1]);
+}
+template <> __device__ __forceinline__ void net_merge<12>(uint32_t *v)
+{
+    constexpr uint8_t n[19][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {2, 6}, {3, 7}, {4, 8}, {5, 9}, {0, 2}, {1, 3},
+                                  {4, 6}, {5, 7}, {8, 10}, {9, 11}, {1, 2}, {3, 4}, {5, 6}, {7, 8}, {9, 10}};
+#pragma unroll
+    for (int c = 0; c < 19; ++c) cx(v, n[c][0], n[c][1]);
+}
+template <> __device__ __forceinline__ void net_sort<13>(uint32_t *v)
+{
+    constexpr uint8_t n[48][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {4, 12}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                  {8, 12}, {4, 8}, {5, 9}, {6, 10}, {7, 11}, {0, 2}, {1, 3}, {4, 6}, {5, 7},
+                                  {8, 10}, {9, 11}, {2, 8}, {3, 9}, {6, 12}, {2, 4}, {3, 5}, {6, 8}, {7, 9},
+                                  {10, 12}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9}, {10, 11}, {1, 8}, {3, 10},
+                                  {5, 12}, {1, 4}, {3, 6}, {5, 8}, {7, 10}, {9, 12}, {1, 2}, {3, 4}, {5, 6},
+                                  {7, 8}, {9, 10}, {11, 12}};
+#pragma unroll
+    for (int c = 0; c < 48; ++c) cx(v, n[c][0], n[c][1]);
+}
+template <> __device__ __forceinline__ void net_merge<13>(uint32_t *v)
+{
+    constexpr uint8_t n[21][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {4, 12}, {3, 7}, {4, 8}, {5, 9}, {6, 10},
+                                  {1, 3}, {5, 7}, {9, 11}, {2, 4}, {6, 8}, {10, 12}, {0, 1}, {2, 3}, {4, 5},
+                                  {6, 7}, {8, 9}, {10, 11}};
+#pragma unroll
+    for (int c = 0; c < 21; ++c) cx(v, n[c][0], n[c][1]);
 }
 
 template <int W>
@@ -277,7 +316,6 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 // Leaves the sorted set in s[0..ke) and returns true, or returns false once
 // J would exceed lim.
 constexpr uint32_t kBucketWords = 512;   // 1024 16-bit counters
-constexpr uint32_t kDump = kFastDraws + 8;   // s[kDump + lane]: writes of ~0 entries
 
 __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t *cnt, uint32_t ke, uint32_t lim)
 {
@@ -307,7 +345,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                 atomicAdd(&cnt[b >> 1], ok ? 1u << ((b & 1) << 4) : 0u);
                 v[q] = ok ? v[q] : kNone;
             }
-            *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
+            if (4 * blk < J) *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
         }
         __syncthreads();
         if (coll) return false;
@@ -334,12 +372,13 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         __syncthreads();
         {
             // every staged draw is loaded before the first one is placed;
-            // a ~0 entry adds 0 and is written to this lane's dump word
+            // a ~0 entry adds 0
             uint32_t x[16];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 uint4 q = make_uint4(kNone, kNone, kNone, kNone);
-                if ((uint32_t)e < nit) q = *reinterpret_cast<const uint4 *>(s + 4 * (lane + 64 * e));
+                if ((uint32_t)e < nit && 4 * (lane + 64 * e) < J)
+                    q = *reinterpret_cast<const uint4 *>(s + 4 * (lane + 64 * e));
                 x[4 * e] = q.x; x[4 * e + 1] = q.y; x[4 * e + 2] = q.z; x[4 * e + 3] = q.w;
             }
             __syncthreads();
@@ -358,7 +397,9 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t xv = x[4 * e + q];
-                        const uint32_t pos = xv != kNone ? (old[q] >> h[q]) & 0xFFFFu : kDump + lane;
+                        // a ~0 entry lands in the padding after the V keys, which is
+                        // rewritten below (every window span exceeds V by at least 4)
+                        const uint32_t pos = xv != kNone ? (old[q] >> h[q]) & 0xFFFFu : V + (lane & 3);
                         s[pos] = xv;
                     }
                 }
@@ -367,17 +408,17 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         __syncthreads();
         uint32_t ndup = 0;
         {
-            // window width and count per lane from V: 8 keys (V <= 512),
-            // 10 keys (V <= 640) or two windows of 8 (V <= 1024)
-            const int mode = V <= 512 ? 0 : V <= 640 ? 1 : 2;
-            const uint32_t span = mode == 0 ? 516 : mode == 1 ? 645 : 1028;
+            // window width from V: 8, 10, 12 or 13 keys per lane
+            const int mode = V <= 512 ? 0 : V <= 640 ? 1 : V <= 768 ? 2 : 3;
+            const uint32_t span = mode == 0 ? 516 : mode == 1 ? 645 : mode == 2 ? 774 : 838;
             for (uint32_t p = V + lane; p < span; p += 64) s[p] = kNone;
             for (;;) {
                 __syncthreads();
                 uint64_t bad;
                 if (mode == 0) bad = windows<8, 1>(s, V, ndup);
                 else if (mode == 1) bad = windows<10, 1>(s, V, ndup);
-                else bad = windows<8, 2>(s, V, ndup);
+                else if (mode == 2) bad = windows<12, 1>(s, V, ndup);
+                else bad = windows<13, 1>(s, V, ndup);
                 __syncthreads();
                 if (!bad) break;
             }
@@ -510,8 +551,8 @@ __device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t
 
 __global__ __launch_bounds__(64) void tile_kernel(Job job)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t s_key[kDump + 64];
-    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords + 4];   // counters
+    __shared__ __attribute__((aligned(16))) uint32_t s_key[kKeyWords];
+    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // 16-bit counters, two per word
     if (ld_uni(job.status + 1)) return;
     const uint64_t T = ld_uni(job.status + 2);
     uint64_t t, t1;
