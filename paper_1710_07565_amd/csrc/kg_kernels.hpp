@@ -392,9 +392,11 @@ struct Decoder {
         }
         const uint64_t l = lbase + x;
         const uint64_t lr = Ttri - 1 - l;
+        // largest q with q(q+1)/2 <= lr: the binary64 estimate is within one
+        // of it for lr < 2^53, so each correction runs at most twice
         uint64_t q = (uint64_t)((sqrt(8.0 * (double)lr + 1.0) - 1.0) * 0.5);
-        while (q * (q + 1) / 2 > lr) --q;
-        while ((q + 1) * (q + 2) / 2 <= lr) ++q;
+        for (int i = 0; i < 2 && q * (q + 1) / 2 > lr; ++i) --q;
+        for (int i = 0; i < 2 && (q + 1) * (q + 2) / 2 <= lr; ++i) ++q;
         const uint64_t r = h - 2 - q;
         const uint64_t st = r * h - r * (r + 1) / 2;
         return make_uint2((uint32_t)(a + r), (uint32_t)(a + r + 1 + (l - st)));

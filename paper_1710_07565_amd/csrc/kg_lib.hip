@@ -208,7 +208,7 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     // planner units: enough of them to give every resident lane one (one lane
     // expands a unit), at most kUnitTiles tiles each
     {
-        const uint64_t lanes = 256ull * 8 * 64;
+        const uint64_t lanes = 256ull * 16 * 64;
         uint32_t ulog = 1;
         while (ulog < 6 && (P.Tb >> (ulog + 1)) >= lanes) ++ulog;
         job.unit_log = ulog;
