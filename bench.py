@@ -377,9 +377,9 @@ def run_serve(args):
         # saturation: double the rate until the p99 latency diverges
         rate = args.rate * 2
         while rate <= args.rate * 64:
-            srv2 = serve.Server(budget_bytes=int(args.budget_gb * 1e9), streams=args.streams,
-                                max_batch=args.max_batch)
-            st2 = serve.run_stream(srv2, workloads.request_stream(rate_per_s=rate, duration_s=args.sweep_seconds,
+            # the same server (one arena of the budget's size), fresh counters
+            srv.rejected = 0
+            st2 = serve.run_stream(srv, workloads.request_stream(rate_per_s=rate, duration_s=args.sweep_seconds,
                                                                   base_seed=2, seed_fn=kg.instance_seed),
                                    warmup_s=min(2.0, args.sweep_seconds / 4))[1]
             sweep.append({"rate_per_s": rate, "edges_per_s": st2["edges_per_s"], "p50_s": st2["p50_s"],

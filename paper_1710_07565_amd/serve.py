@@ -4,7 +4,9 @@ Requests (n, model, directed, m or p, seed, P) arrive over time.  Every tick
 the scheduler admits queued requests in arrival order while their output fits
 the HBM budget, packs them into one kg_batch launch (one pass of the
 generator over all of them) on the next of S streams, and keeps the edge
-lists on the device.  Launches on different streams overlap on the GPU;
+lists on the device.  Output space comes from one device arena of the budget's
+size, allocated once; a first-fit range allocator hands out and takes back
+contiguous ranges, so a launch never allocates device memory of its own.  Launches on different streams overlap on the GPU;
 requests that arrive while others run are admitted as soon as memory frees
 up.  A finished request's latency is completion time minus arrival time;
 its memory returns to the budget when the client releases it.
@@ -44,8 +46,37 @@ class Request:
         self.bound = _edge_bound(spec)
 
 
+class _Ranges:
+    """First-fit allocator of contiguous edge ranges in [0, cap)."""
+
+    def __init__(self, cap):
+        self.free = [(0, cap)]           # sorted, non-adjacent (start, length)
+
+    def alloc(self, n):
+        for i, (a, l) in enumerate(self.free):
+            if l >= n:
+                if l == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (a + n, l - n)
+                return a
+        return None
+
+    def release(self, a, n):
+        import bisect
+        i = bisect.bisect_left(self.free, (a, 0))
+        self.free.insert(i, (a, n))
+        # merge with the neighbours
+        if i + 1 < len(self.free) and self.free[i][0] + self.free[i][1] == self.free[i + 1][0]:
+            self.free[i] = (self.free[i][0], self.free[i][1] + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+
 class _Batch:
-    __slots__ = ("reqs", "arena", "offsets", "event", "stream", "ws", "bytes", "reqs_alive")
+    __slots__ = ("reqs", "start", "cap", "offsets", "event", "stream", "si", "ws", "bytes", "reqs_alive")
 
 
 class Server:
@@ -76,6 +107,12 @@ class Server:
         self.lock = threading.Lock()
         self.nreq = 0
         self.rejected = 0
+        # the output arena and a workspace per stream, allocated once
+        self.arena_edges = self.budget // 8
+        self.arena = torch.empty((self.arena_edges, 2), dtype=torch.uint32, device=self.device)
+        self.ranges = _Ranges(self.arena_edges)
+        self.ws = [None] * streams
+        self.offsets = [torch.empty(max_batch + 1, dtype=torch.uint64, device=self.device) for _ in range(streams)]
 
     # -- client side -------------------------------------------------------
     def submit(self, spec, arrival=None):
@@ -99,7 +136,7 @@ class Server:
                 b.reqs_alive -= 1
                 if b.reqs_alive == 0:
                     self.used -= b.bytes
-                    b.arena = None
+                    self.ranges.release(b.start, b.cap)
 
     # -- scheduler ---------------------------------------------------------
     def _admit(self):
@@ -119,31 +156,43 @@ class Server:
     def _launch(self, reqs, need):
         import ctypes
         torch = self.torch
+        cap = max(sum(r.bound for r in reqs), 1)
+        start = self.ranges.alloc(cap)
+        if start is None:                    # fragmented: wait for releases
+            with self.lock:
+                self.queue.extendleft(reversed(reqs))
+            return False
         now = time.perf_counter()
-        stream = self.streams[self.next_stream]
-        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        # a stream whose previous batch has been reaped (its offsets buffer and
+        # workspace are free again)
+        busy = {b.si for b in self.inflight}
+        si = next(i for i in range(len(self.streams)) if i not in busy)
+        stream = self.streams[si]
         insts = [Instance(r.spec.n, r.spec.model, r.spec.directed, r.spec.m, r.spec.p, r.spec.seed, r.spec.chunks)
                  for r in reqs]
         arr = (KgInstance * len(insts))(*[i.c() for i in insts])
         wsb = ctypes.c_uint64(0)
         _lib.check(_lib.lib().kg_workspace_bytes(arr, len(insts), ctypes.byref(wsb)), "kg_workspace_bytes")
-        cap = sum(r.bound for r in reqs)
         with torch.cuda.stream(stream):
-            arena = torch.empty((max(cap, 1), 2), dtype=torch.uint32, device=self.device)
-            offsets = torch.empty(len(reqs) + 1, dtype=torch.uint64, device=self.device)
-            ws = torch.empty(max(wsb.value, 1), dtype=torch.uint8, device=self.device)
-            st = _lib.lib().kg_batch(arr, len(insts), arena.data_ptr(), cap, offsets.data_ptr(), ws.data_ptr(),
+            if self.ws[si] is None or self.ws[si].numel() < wsb.value:
+                self.ws[si] = torch.empty(max(wsb.value, 1 << 20), dtype=torch.uint8, device=self.device)
+            ws = self.ws[si]
+            offsets = self.offsets[si]
+            view = self.arena[start:start + cap]
+            st = _lib.lib().kg_batch(arr, len(insts), view.data_ptr(), cap, offsets.data_ptr(), ws.data_ptr(),
                                      ws.numel(), _stream(stream))
             _lib.check(st, "kg_batch")
             ev = torch.cuda.Event()
             ev.record(stream)
         b = _Batch()
-        b.reqs, b.arena, b.offsets, b.event, b.stream, b.ws, b.bytes = reqs, arena, offsets, ev, stream, ws, need
+        b.reqs, b.start, b.cap, b.offsets, b.event, b.stream, b.si, b.ws, b.bytes = (reqs, start, cap, offsets, ev,
+                                                                                   stream, si, ws, need)
         self.used += need
         for r in reqs:
             r.admitted = now
             r.batch = b
         self.inflight.append(b)
+        return True
 
     def _reap(self):
         torch = self.torch
@@ -153,13 +202,15 @@ class Server:
                 still.append(b)
                 continue
             now = time.perf_counter()
-            offs = b.offsets.view(torch.int64).cpu().tolist()
-            b.ws = None
+            offs = b.offsets[:len(b.reqs) + 1].view(torch.int64).cpu().tolist()
+            if offs[-1] > b.cap:
+                # a G(n,p) total beyond mean + 10 sd: the launch wrote nothing
+                raise RuntimeError("batch of %d requests needs %d edges, reserved %d" % (len(b.reqs), offs[-1], b.cap))
             b.reqs_alive = len(b.reqs)
             for i, r in enumerate(b.reqs):
                 r.done = now
                 r.offset, r.nedges = offs[i], offs[i + 1] - offs[i]
-                r.edges = b.arena[offs[i]:offs[i + 1]]
+                r.edges = self.arena[b.start + offs[i]:b.start + offs[i + 1]]
                 self.finished.append(r)
                 if self.on_done is not None:
                     self.on_done(r)
@@ -174,8 +225,7 @@ class Server:
         if len(self.inflight) < len(self.streams):
             reqs, need = self._admit()
             if reqs:
-                self._launch(reqs, need)
-                return True
+                return self._launch(reqs, need)
         return False
 
     def drain(self, timeout=600.0):
