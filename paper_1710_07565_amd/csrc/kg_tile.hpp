@@ -241,7 +241,8 @@ __device__ __forceinline__ void wstore(uint32_t *s, uint32_t p0, const uint32_t 
 // merges the windows shifted by W/2 (whose halves are sorted by the first
 // pass).  The result is sorted unless a bucket of more than W/2 + 1 keys
 // lies across a window boundary; every adjacent pair of [0, span) is
-// compared once from registers.  Returns the mask of lanes that saw a pair
+// compared once from registers for repeats, and the pairs across window
+// boundaries (the only places where order can break) for order.  Returns the mask of lanes that saw a pair
 // out of order and adds the equal pairs among the first V positions to dups.
 template <int W, int R>
 __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &dups)
@@ -269,11 +270,10 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
         wload<W>(s, p0, v);
         net_merge<W>(v);
         wstore<W>(s, p0, v);
+        // a merged window is sorted (both halves come sorted from the first
+        // pass): order can break only across window boundaries
 #pragma unroll
-        for (int i = 0; i + 1 < W; ++i) {
-            bad |= __ballot(v[i] > v[i + 1]);
-            eq += __popcll(__ballot(v[i] == v[i + 1]));
-        }
+        for (int i = 0; i + 1 < W; ++i) eq += __popcll(__ballot(v[i] == v[i + 1]));
         if (r == 0) {
             first = v[0];
         } else {
@@ -330,9 +330,24 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         cw[1] = make_uint4(0, 0, 0, 0);
         __syncthreads();
         const uint32_t nit = uni((J + 255) >> 8);
+        // rounds whose 256 draws all lie below J: in a full tile with keys
+        // below 2^31 every such draw is valid and needs no checks
+        const uint32_t nclean = (t.full && t.bits < 32) ? uni(J >> 8) : 0u;
         uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
 #pragma unroll 1
-        for (uint32_t e = 0; e < nit; ++e) {
+        for (uint32_t e = 0; e < nclean; ++e) {
+            const uint32_t blk = lane + 64u * e;
+            const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
+            const uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t b = v[q] >> shift;
+                atomicAdd(&cnt[b >> 1], 1u << ((b & 1) << 4));
+            }
+            *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+#pragma unroll 1
+        for (uint32_t e = nclean; e < nit; ++e) {
             const uint32_t blk = lane + 64u * e;
             const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
             uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
@@ -384,7 +399,18 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if ((uint32_t)e < nit) {
+                if ((uint32_t)e < nclean) {
+                    // every entry of a clean round is a valid key
+                    uint32_t old[4], h[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t b = x[4 * e + q] >> shift;
+                        h[q] = (b & 1) << 4;
+                        old[q] = atomicAdd(&cnt[b >> 1], 1u << h[q]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) s[(old[q] >> h[q]) & 0xFFFFu] = x[4 * e + q];
+                } else if ((uint32_t)e < nit) {
                     uint32_t old[4], h[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
