@@ -306,22 +306,21 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 
 // Base case of the common tiles.  Pass 1 (one Philox block per lane and
 // trip; lane L computes blocks L + 64 e, i.e. draws 256 e + 4 L + q) counts
-// every valid draw in its bucket -- the top min(10, bits) bits of the key,
-// 16-bit counters two to a word -- and stages the draws in s[] (rejected
-// ones as ~0).  An exclusive scan turns the counters into bucket starts.
+// every valid draw in its bucket -- the top min(9, bits) bits of the key,
+// 512 32-bit counters -- and stages the draws in s[] (rejected ones as ~0).  An exclusive scan turns the counters into bucket starts.
 // Pass 2 reloads the staged draws and places each at a position taken from
 // its bucket start by an LDS atomic; the 8-key window passes then sort
 // inside buckets and count repeats.  While fewer than ke distinct values are
 // seen, J grows by the shortfall (each draw adds at most one new value).
 // Leaves the sorted set in s[0..ke) and returns true, or returns false once
 // J would exceed lim.
-constexpr uint32_t kBucketWords = 512;   // 1024 16-bit counters
+constexpr uint32_t kBucketWords = 512;   // one 32-bit counter per bucket
 
 __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t *cnt, uint32_t ke, uint32_t lim)
 {
     const uint32_t lane = threadIdx.x;
     const uint32_t S32 = (uint32_t)t.S;                 // used only when S < 2^bits <= 2^32
-    const uint32_t shift = t.bits > 10 ? t.bits - 10 : 0;
+    const uint32_t shift = t.bits > 9 ? t.bits - 9 : 0;
     uint4 *cw = reinterpret_cast<uint4 *>(cnt) + 2 * lane;   // this lane's 8 counter words
     uint32_t J = ke;
     for (;;) {
@@ -341,8 +340,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             const uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint32_t b = v[q] >> shift;
-                atomicAdd(&cnt[b >> 1], 1u << ((b & 1) << 4));
+                atomicAdd(&cnt[v[q] >> shift], 1u);
             }
             *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
         }
@@ -356,8 +354,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                 // branch-free: a draw past J or rejected adds 0 and is staged as ~0
                 const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
                 coll |= __ballot(ok & (v[q] == kNone));
-                const uint32_t b = v[q] >> shift;
-                atomicAdd(&cnt[b >> 1], ok ? 1u << ((b & 1) << 4) : 0u);
+                atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
                 v[q] = ok ? v[q] : kNone;
             }
             if (4 * blk < J) *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
@@ -368,18 +365,13 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         {
             const uint4 c0 = cw[0], c1 = cw[1];
             uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-            uint32_t packed = 0;
+            uint32_t sum = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) packed += w[i];      // halves cannot carry: totals <= 1024
-            const uint32_t sum = (packed & 0xFFFFu) + (packed >> 16);
+            for (int i = 0; i < 8; ++i) sum += w[i];
             const uint32_t incl = wave_incl_scan32(sum);
             uint32_t run = incl - sum;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint32_t lo = w[i] & 0xFFFFu, hi = w[i] >> 16;
-                w[i] = run | ((run + lo) << 16);
-                run += lo + hi;
-            }
+            for (int i = 0; i < 8; ++i) { const uint32_t c = w[i]; w[i] = run; run += c; }
             cw[0] = make_uint4(w[0], w[1], w[2], w[3]);
             cw[1] = make_uint4(w[4], w[5], w[6], w[7]);
             V = __builtin_amdgcn_readlane(incl, 63);
@@ -401,31 +393,25 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             for (int e = 0; e < 4; ++e) {
                 if ((uint32_t)e < nclean) {
                     // every entry of a clean round is a valid key
-                    uint32_t old[4], h[4];
+                    uint32_t old[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t b = x[4 * e + q] >> shift;
-                        h[q] = (b & 1) << 4;
-                        old[q] = atomicAdd(&cnt[b >> 1], 1u << h[q]);
-                    }
+                    for (int q = 0; q < 4; ++q) old[q] = atomicAdd(&cnt[x[4 * e + q] >> shift], 1u);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) s[(old[q] >> h[q]) & 0xFFFFu] = x[4 * e + q];
+                    for (int q = 0; q < 4; ++q) s[old[q]] = x[4 * e + q];
                 } else if ((uint32_t)e < nit) {
-                    uint32_t old[4], h[4];
+                    uint32_t old[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t xv = x[4 * e + q];
                         const bool ok = xv != kNone;
-                        const uint32_t b = ok ? xv >> shift : 0u;   // b < 1024
-                        h[q] = (b & 1) << 4;
-                        old[q] = atomicAdd(&cnt[b >> 1], ok ? 1u << h[q] : 0u);
+                        old[q] = atomicAdd(&cnt[ok ? xv >> shift : 0u], ok ? 1u : 0u);
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t xv = x[4 * e + q];
                         // a ~0 entry lands in the padding after the V keys, which is
                         // rewritten below (every window span exceeds V by at least 4)
-                        const uint32_t pos = xv != kNone ? (old[q] >> h[q]) & 0xFFFFu : V + (lane & 3);
+                        const uint32_t pos = xv != kNone ? old[q] : V + (lane & 3);
                         s[pos] = xv;
                     }
                 }
@@ -578,7 +564,7 @@ __device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t
 __global__ __launch_bounds__(64) void tile_kernel(Job job)
 {
     __shared__ __attribute__((aligned(16))) uint32_t s_key[kKeyWords];
-    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // 16-bit counters, two per word
+    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // bucket counters, then starts
     if (ld_uni(job.status + 1)) return;
     const uint64_t T = ld_uni(job.status + 2);
     uint64_t t, t1;
