@@ -105,6 +105,26 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
                    uint64_t arena_edges, uint64_t *d_inst_offsets,
                    void *d_workspace, uint64_t workspace_bytes, void *stream);
 
+/* kg_batch in two parts, so that the generating part can be recorded into a
+ * HIP graph (stream capture) and replayed.  kg_batch_upload writes the
+ * descriptor table of the list into d_workspace (required, at least
+ * kg_workspace_bytes) and synchronises `stream`; it must not be called while
+ * `stream` is capturing.  kg_batch_launch then does what kg_batch does with
+ * the same arguments and output, but reads the descriptor table from the
+ * workspace and enqueues kernels only: no allocation, no host copy, no
+ * synchronisation.  It must be given the same list (h_inst is read on the
+ * host for the launch sizes) and a workspace that the upload filled and that
+ * nothing else has used since; while `stream` is capturing, the library must
+ * already have been used once on the device (any call) and every call but
+ * kg_batch_launch, kg_gnm, kg_gnp and kg_chunk_counts with a caller
+ * workspace is refused (KG_EINVAL).  A replayed graph rewrites the same bytes;
+ * replays that overlap in time must not share the arena or the workspace. */
+kg_status kg_batch_upload(const kg_instance *h_inst, uint32_t count, void *d_workspace,
+                          uint64_t workspace_bytes, void *stream);
+kg_status kg_batch_launch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
+                          uint64_t arena_edges, uint64_t *d_inst_offsets,
+                          void *d_workspace, uint64_t workspace_bytes, void *stream);
+
 /* Per-instance seed of a batch drawn from a base seed: the Philox4x32-10
  * image of counter (0, i, 0, 6) under key `base`, words (w1:w0). Host only. */
 uint64_t kg_instance_seed(uint64_t base, uint32_t i);

@@ -165,6 +165,49 @@ def batch(instances, arena=None, offsets=None, workspace=None, stream=None, devi
     return arena, offsets
 
 
+def batch_upload(instances, workspace, stream=None):
+    """Write the descriptor table of `instances` into `workspace` (a device
+    uint8 tensor of at least workspace_bytes(instances)); synchronises."""
+    cnt = len(instances)
+    arr = (KgInstance * cnt)(*[i.c() for i in instances])
+    _lib.check(_lib.lib().kg_batch_upload(arr, cnt, workspace.data_ptr(), workspace.numel(), _stream(stream)),
+               "kg_batch_upload")
+
+
+def batch_launch(instances, arena, offsets, workspace, stream=None):
+    """The kernels of batch() for a list already uploaded to `workspace`:
+    enqueues kernels only, so it may run under stream capture."""
+    cnt = len(instances)
+    arr = (KgInstance * cnt)(*[i.c() for i in instances])
+    st = _lib.lib().kg_batch_launch(arr, cnt, arena.data_ptr() if arena.numel() else None, arena.shape[0],
+                                    offsets.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream))
+    _lib.check(st, "kg_batch_launch")
+
+
+class BatchGraph:
+    """A batch recorded once into a HIP graph (torch.cuda.CUDAGraph) and
+    replayed: the arena, offsets and workspace are fixed at construction and
+    every replay rewrites the same bytes.  The graph holds kernel launches
+    only; the descriptor table is uploaded before the capture."""
+
+    def __init__(self, instances, arena, offsets, workspace):
+        torch = _torch()
+        self.instances = list(instances)
+        self.arena, self.offsets, self.workspace = arena, offsets, workspace
+        batch_upload(self.instances, workspace)
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=arena.device)
+        side.wait_stream(torch.cuda.current_stream(arena.device))
+        with torch.cuda.graph(self.graph, stream=side):
+            batch_launch(self.instances, arena, offsets, workspace)
+        torch.cuda.current_stream(arena.device).wait_stream(side)
+
+    def replay(self):
+        """Enqueue the recorded kernels on the current stream."""
+        self.graph.replay()
+        return self.arena, self.offsets
+
+
 def eval_device(fn, d_in, n, out_dtype, out_width, stream=None):
     """Element-wise evaluation of a device building block (see kg_eval)."""
     torch = _torch()

@@ -36,13 +36,21 @@ int64_t g_time_kernels = 0;
 std::mutex g_time_mu;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events[5];
 
+// True while `s` is being recorded into a graph: such a call must only
+// enqueue kernels (no allocation, synchronisation or host-memory copies).
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 struct KernelTimer {
     int id;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     KernelTimer(int kid, hipStream_t st) : id(kid), s(st)
     {
-        if (!g_time_kernels) return;
+        if (!g_time_kernels || capturing(s)) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
         (void)hipEventRecord(a, s);
     }
@@ -228,10 +236,11 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     return job;
 }
 
-// count + scan (+ instance offsets).
-kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s)
+// count + scan (+ instance offsets).  `resident`: the descriptor table is
+// already in the workspace (kg_batch_upload).
+kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s, bool resident)
 {
-    if (job.ninst > 1) {
+    if (job.ninst > 1 && !resident) {
         if (hipMemcpyAsync((void *)job.insts, P.insts.data(), P.insts.size() * sizeof(Inst),
                            hipMemcpyHostToDevice, s) != hipSuccess)
             return KG_EDEVICE;
@@ -280,15 +289,27 @@ kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
 
 kg_status run(const kg_instance *inst, uint32_t count, uint32_t *edges, uint64_t capacity,
               uint64_t *d_total, uint64_t *d_inst_off, void *d_ws, uint64_t ws_bytes, void *stream,
-              bool counts_only, uint64_t *h_total, uint64_t *d_counts)
+              bool counts_only, uint64_t *h_total, uint64_t *d_counts, bool resident = false)
 {
     Prepared P;
     kg_status st = prepare(inst, count, P);
     if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) {
+        // a graph may hold kernels only: the device must be set up, the
+        // workspace given, the descriptor table resident, nothing read back
+        int d = 0;
+        if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return KG_EDEVICE;
+        bool ready;
+        {
+            std::lock_guard<std::mutex> lk(g_init_mu);
+            ready = g_init_done[d];
+        }
+        if (!ready || !d_ws || counts_only || (count > 1 && !resident)) return KG_EINVAL;
+    }
     int dev = 0;
     st = ensure_init(&dev);
     if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
     Workspace ws;
     st = acquire(ws, d_ws, ws_bytes, P.L.total, s);
     if (st) return st;
@@ -305,7 +326,7 @@ kg_status run(const kg_instance *inst, uint32_t count, uint32_t *edges, uint64_t
         release(ws, s);
         return st;
     }
-    st = launch_counts(P, job, s);
+    st = launch_counts(P, job, s, resident);
     if (!st && counts_only) {
         uint64_t tot = 0;
         if (hipMemcpyAsync(&tot, job.status, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -413,6 +434,37 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
     if (!d_arena) arena_edges = 0;
     return run(h_inst, count, d_arena, arena_edges, nullptr, d_inst_offsets, d_workspace, workspace_bytes,
                stream, false, nullptr, nullptr);
+}
+
+kg_status kg_batch_upload(const kg_instance *h_inst, uint32_t count, void *d_workspace,
+                          uint64_t workspace_bytes, void *stream)
+{
+    if (!h_inst || count == 0 || !d_workspace) return KG_EINVAL;
+    Prepared P;
+    kg_status st = prepare(h_inst, count, P);
+    if (st) return st;
+    if (workspace_bytes < P.L.total) return KG_ENOSPC;
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) return KG_EINVAL;
+    int dev = 0;
+    st = ensure_init(&dev);
+    if (st) return st;
+    if (count == 1) return KG_OK;          // one instance travels in the kernel arguments
+    if (hipMemcpyAsync((char *)d_workspace + P.L.insts, P.insts.data(), P.insts.size() * sizeof(Inst),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return KG_EDEVICE;
+    return KG_OK;
+}
+
+kg_status kg_batch_launch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena, uint64_t arena_edges,
+                          uint64_t *d_inst_offsets, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!h_inst || count == 0 || !d_inst_offsets || !d_workspace) return KG_EINVAL;
+    if (((uintptr_t)d_arena & 7) != 0) return KG_EINVAL;
+    if (!d_arena) arena_edges = 0;
+    return run(h_inst, count, d_arena, arena_edges, nullptr, d_inst_offsets, d_workspace, workspace_bytes,
+               stream, false, nullptr, nullptr, true);
 }
 
 uint64_t kg_instance_seed(uint64_t base, uint32_t i)
