@@ -302,6 +302,16 @@ def run_batch(args):
             k = j % nstreams
             kg.batch([insts[i] for i in w], arena=arenas[k], offsets=offss[k], workspace=wss[k], stream=streams[k])
 
+    tuning = None
+    if not args.no_tune:
+        # launch shapes from the autotuner, timed on a spread of the instances
+        # (bit-invariant; recorded graphs keep the shapes in force at capture)
+        from paper_1710_07565_amd import tune
+        pick = [insts[i] for i in range(0, len(insts), max(1, len(insts) // 64))]
+        res = tune.tune(pick, device=dev)
+        tuning = {"sample_instances": len(pick), "sample_edges": res["edges"], "best": res["best"],
+                  "candidates": len(res["table"])}
+        log("bench: tuned launch shape %s" % (res["best"],))
     # one HIP graph per wave, recorded once (descriptor table uploaded into a
     # workspace of its own), replayed on the wave's stream
     graphs = []
@@ -384,6 +394,7 @@ def run_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": BYTES_PER_EDGE * E / (samp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": None, "kernel": ROOFLINE_KERNEL, "avg_launch_ms": samp_ms / max(samp_n, 1)},
+        "tuning": tuning,
         "graphs": {"one_graph_replay_per_wave": True, "eager_kg_batch_edges_per_s": E * args.steps / (ms_eager * 1e-3),
                    "eager_ms_per_step": ms_eager / args.steps},
         "batching": {"sample_instances": len(sample), "sample_edges": E_sample,
@@ -455,6 +466,7 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=256)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--no-tune", action="store_true", help="batch mode: keep the default launch shapes")
     ap.add_argument("--sweep", action="store_true", help="serve mode: also sweep the arrival rate up to saturation")
     ap.add_argument("--sweep-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
