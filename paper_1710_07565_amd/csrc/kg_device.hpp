@@ -216,17 +216,25 @@ __device__ __forceinline__ double stirling_diff(uint64_t a, uint64_t d)
     return (t1 + t2) + t3;
 }
 
-// lnf(y) - lnf(x).
+// lnf(y) - lnf(x).  Both cases above the table go through one Stirling
+// difference (lanes of a wave often differ in the case): from x itself, or
+// from the end of the table with the tabulated part below it added; in the
+// first case the added part is +0.0, which leaves the value unchanged.
 __device__ __forceinline__ double lnf_diff(uint64_t x, uint64_t y)
 {
     if (x == y) return 0.0;
-    double sign = 1.0;
-    if (x > y) { const uint64_t t = x; x = y; y = t; sign = -1.0; }
+    const bool neg = x > y;
+    const uint64_t lo = neg ? y : x, hi = neg ? x : y;
     double r;
-    if (y <= kLnfTab)      r = g_lnf_tab[y] - g_lnf_tab[x];
-    else if (x >= kLnfTab) r = stirling_diff(x, y - x);
-    else                   r = (g_lnf_tab[kLnfTab] - g_lnf_tab[x]) + stirling_diff(kLnfTab, y - kLnfTab);
-    return sign < 0.0 ? -r : r;
+    if (hi <= kLnfTab) {
+        r = g_lnf_tab[hi] - g_lnf_tab[lo];
+    } else {
+        const bool part = lo < kLnfTab;
+        const uint64_t a = part ? (uint64_t)kLnfTab : lo;
+        const double tp = part ? g_lnf_tab[kLnfTab] - g_lnf_tab[part ? lo : 0] : 0.0;
+        r = tp + stirling_diff(a, hi - a);
+    }
+    return neg ? -r : r;
 }
 
 // floor(a * b / d) for a*b < 2^106, d >= 1, exactly: estimate in binary64,

@@ -236,70 +236,62 @@ __device__ __forceinline__ void wstore(uint32_t *s, uint32_t p0, const uint32_t 
     for (int i = 0; i < W; ++i) s[p0 + i] = v[i];
 }
 
-// Window passes over s[0..span), span = 64 W R + W/2, positions V.. padded
-// with ~0 (no key equals ~0).  Lane L sorts windows [W (R L + r), +W), then
-// merges the windows shifted by W/2 (whose halves are sorted by the first
-// pass).  The result is sorted unless a bucket of more than W/2 + 1 keys
-// lies across a window boundary; every adjacent pair of [0, span) is
-// compared once from registers for repeats, and the pairs across window
-// boundaries (the only places where order can break) for order.  Returns the mask of lanes that saw a pair
-// out of order and adds the equal pairs among the first V positions to dups.
-template <int W, int R>
+// Lane-to-lane moves of the merge step (wave-wide DPP shifts by one lane);
+// the lane without a source keeps `edge`.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x, uint32_t edge)
+{
+    return __builtin_amdgcn_update_dpp(edge, x, 0x130, 0xF, 0xF, false);   // wave_shl:1, lane 63 keeps edge
+}
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x, uint32_t edge)
+{
+    return __builtin_amdgcn_update_dpp(edge, x, 0x138, 0xF, 0xF, false);   // wave_shr:1, lane 0 keeps edge
+}
+
+// One window pass over s[0..span), span = 64 W + W/2, positions V.. padded
+// with ~0 (no key equals ~0).  Lane L loads window [W L, +W) and sorts it;
+// the windows shifted by H = W/2 (this lane's last W - H keys and the next
+// lane's first H, both sorted) are merged in registers, the next lane's part
+// travelling there and back by DPP; the result is stored in place.  It is
+// sorted unless a bucket of more than H + 1 keys lies across a window
+// boundary; every adjacent pair of [0, span) is compared once for repeats,
+// and the pairs between merged windows (the only places where order can
+// break) for order.  Returns the mask of lanes that saw a pair out of order
+// and sets dups to the equal pairs among the first V positions.
+template <int W>
 __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &dups)
 {
-    constexpr int H = W / 2;
+    constexpr int H = W / 2, U = W - H;
     const uint32_t lane = threadIdx.x;
-    uint32_t v[W], head[H];
+    const uint32_t p0 = W * lane;
+    uint32_t v[W], m[W];
+    wload<W>(s, p0, v);
+    net_sort<W>(v);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t p0 = W * (R * lane + r);
-        wload<W>(s, p0, v);
-        net_sort<W>(v);
-        wstore<W>(s, p0, v);
-        if (r == 0) {
+    for (int i = 0; i < U; ++i) m[i] = v[H + i];
 #pragma unroll
-            for (int i = 0; i < H; ++i) head[i] = v[i];
-        }
-    }
-    __syncthreads();
-    uint64_t bad = 0;
-    uint32_t eq = 0, first = 0, last = 0;
+    for (int i = 0; i < H; ++i) m[U + i] = from_next_lane(v[i], kNone);   // lane 63: the padding
+    net_merge<W>(m);
+    uint32_t eq = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t p0 = W * (R * lane + r) + H;
-        wload<W>(s, p0, v);
-        net_merge<W>(v);
-        wstore<W>(s, p0, v);
-        // a merged window is sorted (both halves come sorted from the first
-        // pass): order can break only across window boundaries
+    for (int i = 0; i + 1 < W; ++i) eq += __popcll(__ballot(m[i] == m[i + 1]));
+    // this lane keeps the merged window's lower part; the upper part goes
+    // back to the next lane (lane 0 keeps its sorted head)
 #pragma unroll
-        for (int i = 0; i + 1 < W; ++i) eq += __popcll(__ballot(v[i] == v[i + 1]));
-        if (r == 0) {
-            first = v[0];
-        } else {
-            bad |= __ballot(last > v[0]);
-            eq += __popcll(__ballot(last == v[0]));
-        }
-        last = v[W - 1];
-    }
-    // lane boundaries, and the head [0, H) of lane 0's first window
-    const uint32_t nxt = __shfl_down(first, 1, 64);
-    const bool inner = lane < 63;
-    bad |= __ballot(inner && last > nxt);
-    eq += __popcll(__ballot(inner && last == nxt));
-    uint32_t hb = 0, he = 0;
+    for (int i = 0; i < U; ++i) v[H + i] = m[i];
+#pragma unroll
+    for (int i = 0; i < H; ++i) v[i] = from_prev_lane(m[U + i], v[i]);
+    wstore<W>(s, p0, v);
+    // between merged windows, and inside lane 0's head
+    uint64_t bad = __ballot(v[H - 1] > v[H]);
+    eq += __popcll(__ballot(v[H - 1] == v[H]));
+    uint32_t he = 0;
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < H; ++i) {
-            const uint32_t y = i + 1 < H ? head[i + 1] : first;
-            hb |= head[i] > y;
-            he += head[i] == y;
-        }
+        for (int i = 0; i + 1 < H; ++i) he += v[i] == v[i + 1];
     }
-    bad |= __ballot(hb != 0);
     eq += __builtin_amdgcn_readfirstlane(he);
     // pairs inside the padding [V, span) are all equal; the pair (V - 1, V) is not
-    constexpr uint32_t span = 64 * W * R + H;
+    constexpr uint32_t span = 64 * W + H;
     dups = eq - (span - 1 - V);
     return bad;
 }
@@ -315,6 +307,7 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 // Leaves the sorted set in s[0..ke) and returns true, or returns false once
 // J would exceed lim.
 constexpr uint32_t kBucketWords = 512;   // one 32-bit counter per bucket
+constexpr uint32_t kWindowPasses = 64;   // bound on window passes per tile
 
 __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t *cnt, uint32_t ke, uint32_t lim)
 {
@@ -424,13 +417,18 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             const int mode = V <= 512 ? 0 : V <= 640 ? 1 : V <= 768 ? 2 : 3;
             const uint32_t span = mode == 0 ? 516 : mode == 1 ? 645 : mode == 2 ? 774 : 838;
             for (uint32_t p = V + lane; p < span; p += 64) s[p] = kNone;
-            for (;;) {
+            // one or two passes sort a tile in practice; one still unsorted
+            // after kWindowPasses passes goes to the queue (the general path
+            // gives the same bits), so the loop always ends
+            uint32_t pass = 0;
+            for (;; ++pass) {
+                if (pass == kWindowPasses) return false;
                 __syncthreads();
                 uint64_t bad;
-                if (mode == 0) bad = windows<8, 1>(s, V, ndup);
-                else if (mode == 1) bad = windows<10, 1>(s, V, ndup);
-                else if (mode == 2) bad = windows<12, 1>(s, V, ndup);
-                else bad = windows<13, 1>(s, V, ndup);
+                if (mode == 0) bad = windows<8>(s, V, ndup);
+                else if (mode == 1) bad = windows<10>(s, V, ndup);
+                else if (mode == 2) bad = windows<12>(s, V, ndup);
+                else bad = windows<13>(s, V, ndup);
                 __syncthreads();
                 if (!bad) break;
             }
@@ -519,12 +517,15 @@ __device__ __forceinline__ void emit_narrow(const TileCtx &t, const uint32_t *s,
     uint2 *out = reinterpret_cast<uint2 *>(t.edges) + t.o0;
     const uint32_t lane = threadIdx.x;
     const uint32_t nfull = n & ~255u;
-    for (uint32_t b = 0; b < nfull; b += 256) {
+    // one 64-bit lane pointer advanced per round; the four stores of a round
+    // sit at fixed byte offsets from it (0, 512, 1024, 1536)
+    uint2 *ol = out + lane;
+    for (uint32_t b = 0; b < nfull; b += 256, ol += 256) {
         uint32_t x[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) x[i] = s[b + lane + 64 * i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[b + lane + 64 * i] = dec_narrow<TYPE, POW2>(d, x[i]);
+        for (int i = 0; i < 4; ++i) ol[64 * i] = dec_narrow<TYPE, POW2>(d, x[i]);
     }
     if (nfull < n) {
         uint32_t x[4];
