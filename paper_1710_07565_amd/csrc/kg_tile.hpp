@@ -297,12 +297,13 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 }
 
 // Base case of the common tiles.  Pass 1 (one Philox block per lane and
-// trip; lane L computes blocks L + 64 e, i.e. draws 256 e + 4 L + q) counts
+// round; lane L computes blocks L + 64 e, i.e. draws 256 e + 4 L + q) counts
 // every valid draw in its bucket -- the top min(9, bits) bits of the key,
-// 512 32-bit counters -- and stages the draws in s[] (rejected ones as ~0).  An exclusive scan turns the counters into bucket starts.
-// Pass 2 reloads the staged draws and places each at a position taken from
-// its bucket start by an LDS atomic; the 8-key window passes then sort
-// inside buckets and count repeats.  While fewer than ke distinct values are
+// 512 32-bit counters -- and keeps the draws in registers (rejected ones as
+// ~0).  An exclusive scan turns the counters into bucket starts.  Pass 2
+// places each draw at a position taken from its bucket start by an LDS
+// atomic; the window passes (8 to 13 keys per lane) then sort inside
+// buckets and count repeats.  While fewer than ke distinct values are
 // seen, J grows by the shortfall (each draw adds at most one new value).
 // Leaves the sorted set in s[0..ke) and returns true, or returns false once
 // J would exceed lim.
@@ -326,31 +327,32 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         // below 2^31 every such draw is valid and needs no checks
         const uint32_t nclean = (t.full && t.bits < 32) ? uni(J >> 8) : 0u;
         uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
-#pragma unroll 1
-        for (uint32_t e = 0; e < nclean; ++e) {
-            const uint32_t blk = lane + 64u * e;
-            const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
-            const uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+        // the draws stay in registers (x[4 e + q] = draw 256 e + 4 lane + q)
+        uint32_t x[16];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                atomicAdd(&cnt[v[q] >> shift], 1u);
-            }
-            *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
-        }
-#pragma unroll 1
-        for (uint32_t e = nclean; e < nit; ++e) {
-            const uint32_t blk = lane + 64u * e;
-            const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
-            uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+        for (int e = 0; e < 4; ++e) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // branch-free: a draw past J or rejected adds 0 and is staged as ~0
-                const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
-                coll |= __ballot(ok & (v[q] == kNone));
-                atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
-                v[q] = ok ? v[q] : kNone;
+            for (int q = 0; q < 4; ++q) x[4 * e + q] = kNone;
+            if ((uint32_t)e < nit) {
+                const uint32_t blk = lane + 64u * e;
+                const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
+                uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+                if ((uint32_t)e < nclean) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) atomicAdd(&cnt[v[q] >> shift], 1u);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // branch-free: a draw past J or rejected adds 0 and is kept as ~0
+                        const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
+                        coll |= __ballot(ok & (v[q] == kNone));
+                        atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
+                        v[q] = ok ? v[q] : kNone;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[4 * e + q] = v[q];
             }
-            if (4 * blk < J) *reinterpret_cast<uint4 *>(s + 4 * blk) = make_uint4(v[0], v[1], v[2], v[3]);
         }
         __syncthreads();
         if (coll) return false;
@@ -371,17 +373,6 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         }
         __syncthreads();
         {
-            // every staged draw is loaded before the first one is placed;
-            // a ~0 entry adds 0
-            uint32_t x[16];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                uint4 q = make_uint4(kNone, kNone, kNone, kNone);
-                if ((uint32_t)e < nit && 4 * (lane + 64 * e) < J)
-                    q = *reinterpret_cast<const uint4 *>(s + 4 * (lane + 64 * e));
-                x[4 * e] = q.x; x[4 * e + 1] = q.y; x[4 * e + 2] = q.z; x[4 * e + 3] = q.w;
-            }
-            __syncthreads();
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if ((uint32_t)e < nclean) {
