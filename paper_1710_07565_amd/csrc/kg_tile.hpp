@@ -300,10 +300,11 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 // round; lane L computes blocks L + 64 e, i.e. draws 256 e + 4 L + q) counts
 // every valid draw in its bucket -- the top min(9, bits) bits of the key,
 // 512 32-bit counters -- and keeps the draws in registers (rejected ones as
-// ~0).  An exclusive scan turns the counters into bucket starts.  Pass 2
-// places each draw at a position taken from its bucket start by an LDS
-// atomic; the window passes (8 to 13 keys per lane) then sort inside
-// buckets and count repeats.  While fewer than ke distinct values are
+// ~0), together with its rank among the draws of its bucket (the value
+// the LDS atomic returned).  An exclusive scan turns the counters into bucket
+// starts; pass 2 places each draw at its bucket start plus its rank; the
+// window passes (8 to 13 keys per lane) then sort inside buckets and count
+// repeats.  While fewer than ke distinct values are
 // seen, J grows by the shortfall (each draw adds at most one new value).
 // Leaves the sorted set in s[0..ke) and returns true, or returns false once
 // J would exceed lim.
@@ -328,25 +329,25 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         const uint32_t nclean = (t.full && t.bits < 32) ? uni(J >> 8) : 0u;
         uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
         // the draws stay in registers (x[4 e + q] = draw 256 e + 4 lane + q)
-        uint32_t x[16];
+        uint32_t x[16], rk[16];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[4 * e + q] = kNone;
+            for (int q = 0; q < 4; ++q) { x[4 * e + q] = kNone; rk[4 * e + q] = 0; }
             if ((uint32_t)e < nit) {
                 const uint32_t blk = lane + 64u * e;
                 const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
                 uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
                 if ((uint32_t)e < nclean) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) atomicAdd(&cnt[v[q] >> shift], 1u);
+                    for (int q = 0; q < 4; ++q) rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], 1u);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         // branch-free: a draw past J or rejected adds 0 and is kept as ~0
                         const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
                         coll |= __ballot(ok & (v[q] == kNone));
-                        atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
+                        rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
                         v[q] = ok ? v[q] : kNone;
                     }
                 }
@@ -379,7 +380,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                     // every entry of a clean round is a valid key
                     uint32_t old[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) old[q] = atomicAdd(&cnt[x[4 * e + q] >> shift], 1u);
+                    for (int q = 0; q < 4; ++q) old[q] = cnt[x[4 * e + q] >> shift] + rk[4 * e + q];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) s[old[q]] = x[4 * e + q];
                 } else if ((uint32_t)e < nit) {
@@ -388,7 +389,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t xv = x[4 * e + q];
                         const bool ok = xv != kNone;
-                        old[q] = atomicAdd(&cnt[ok ? xv >> shift : 0u], ok ? 1u : 0u);
+                        old[q] = cnt[ok ? xv >> shift : 0u] + rk[4 * e + q];
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
