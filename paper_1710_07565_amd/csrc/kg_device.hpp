@@ -67,6 +67,13 @@ __device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k)
 __device__ __forceinline__ U4 philox_uniform_key(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                                  uint32_t k1)
 {
+    // the round keys are formed anew in every call: adding an opaque zero
+    // keeps the compiler from hoisting all twenty of them into scalar
+    // registers for a whole loop, which pushed other scalars into spills
+    uint32_t z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    k0 += z;
+    k1 += z;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
