@@ -554,7 +554,9 @@ __device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t
     t1 = t0 + per < T ? t0 + per : T;
 }
 
-__global__ __launch_bounds__(64) void tile_kernel(Job job)
+// 6 waves per SIMD (at most 80 VGPRs; a few cold values spill to scratch)
+// run faster than 5 waves without spills or 7 waves with many
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void tile_kernel(Job job)
 {
     __shared__ __attribute__((aligned(16))) uint32_t s_key[kKeyWords];
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // bucket counters, then starts
