@@ -320,9 +320,8 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
     uint32_t J = ke;
     for (;;) {
         if (J > lim) return false;
-        cw[0] = make_uint4(0, 0, 0, 0);
-        cw[1] = make_uint4(0, 0, 0, 0);
-        __syncthreads();
+        // the counters are zero here: cleared at the start of the kernel and
+        // after every use (below)
         const uint32_t nit = uni((J + 255) >> 8);
         // rounds whose 256 draws all lie below J: in a full tile with keys
         // below 2^31 every such draw is valid and needs no checks
@@ -356,7 +355,11 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             }
         }
         __syncthreads();
-        if (coll) return false;
+        if (coll) {
+            cw[0] = make_uint4(0, 0, 0, 0);
+            cw[1] = make_uint4(0, 0, 0, 0);
+            return false;
+        }
         uint32_t V;             // valid draws
         {
             const uint4 c0 = cw[0], c1 = cw[1];
@@ -402,6 +405,10 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                 }
             }
         }
+        // the wave's LDS operations complete in order, so the bucket starts
+        // read above are read before they are cleared here
+        cw[0] = make_uint4(0, 0, 0, 0);
+        cw[1] = make_uint4(0, 0, 0, 0);
         __syncthreads();
         uint32_t ndup = 0;
         {
@@ -565,6 +572,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     uint64_t t, t1;
     tile_range(T, t, t1);
     if (t >= t1) return;
+    {
+        uint4 *cw = reinterpret_cast<uint4 *>(s_cnt) + 2 * threadIdx.x;
+        cw[0] = make_uint4(0, 0, 0, 0);
+        cw[1] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+    }
     const uint32_t lim = job.leaf_cap < kFastDraws ? job.leaf_cap : kFastDraws;
     // chunk of the first tile: last g with tstart[g] <= t
     uint64_t g;
