@@ -20,7 +20,8 @@
  *     not depend on the stream, the launch shape, tuning knobs or the device.
  *   - Limits: n <= 2^32, slot count N = n(n-1) (directed) or n(n-1)/2
  *     (undirected) below 2^53, 1 <= P <= n, P <= 2^31 directed, P <= 2^15
- *     undirected.
+ *     undirected; at most 2^36 chunks in one call (a batch counts the
+ *     chunks of all its instances).
  *   - Every device pointer is owned by the caller; the library never frees
  *     caller memory.  `stream` is a hipStream_t (NULL = default stream).
  *     Calls are asynchronous on `stream` unless stated otherwise; argument

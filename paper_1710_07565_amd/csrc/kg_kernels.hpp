@@ -25,6 +25,8 @@ struct Job {
     uint64_t *off;           // G + 1: counts, then exclusive offsets
     uint64_t *tstart;        // G + 1: tiles per chunk, then first tile
     uint64_t *ustart;        // G + 1: planner units per chunk, then first unit
+    uint64_t *bsum;          // 3 x (G / 64 rounded up): per 64 chunks the sums of
+                             // off, tstart, ustart, then their exclusive prefixes
     uint64_t *tile_off;      // output offset of every tile, + total
     uint64_t *status;        // [0] edges [1] overflow [2] tiles [3] units [4] queued tiles
     uint64_t *queue;         // tile_cap entries: tiles left to the general base case
@@ -77,42 +79,7 @@ __global__ void lnf_init_kernel()
     }
 }
 
-// ---------------------------------------------------------------------------
-// count: one lane per chunk.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void count_kernel(Job job)
-{
-    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x;
-    if (g >= job.G) return;
-    const uint32_t i = inst_of_chunk(job, g);
-    const Inst &I = inst_at(job, i);
-    const uint64_t c = g - I.chunk_base;
-    const Chunk ch = chunk_geometry(I, c);
-    uint64_t cnt;
-    if (I.model == 1) {
-        cnt = binom(make_stream(I.seed, (uint32_t)c, 0, TAG_CBIN), ch.N, I.p);
-    } else if (I.directed) {
-        cnt = dtree_count(I, c);
-    } else {
-        uint64_t lo = 0, hi = I.P;
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (uord(I.P, mid) <= c) lo = mid; else hi = mid;
-        }
-        cnt = utree_count(I, lo, lo + (c - uord(I.P, lo)));
-    }
-    const uint64_t T = tiles_of(ch.N, I.s);
-    job.off[g] = cnt;
-    job.tstart[g] = T;
-    job.ustart[g] = T ? (1ull << unit_depth(T, job.unit_log)) : 0;
-}
-
-// ---------------------------------------------------------------------------
-// scan: one workgroup of 1024 lanes walks the three per-chunk arrays in
-// rounds of 4096 entries (four consecutive entries per lane, coalesced):
-// per-lane sums, wave scans, a scan of the 16 wave totals, a running carry.
-// The next round's entries are loaded before the current round is scanned.
-// ---------------------------------------------------------------------------
+// Inclusive sum over the 64 lanes of a wave (shuffles up by 1, 2, ..., 32).
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -124,12 +91,62 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v)
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// count: one lane per chunk (a wave per 64 chunks).  Writes the chunk's edge
+// count, tile count and planner-unit count, and the wave's three sums to
+// bsum (the first phase of the offset scan).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void count_kernel(Job job)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    uint64_t cnt = 0, T = 0, Us = 0;
+    if (g < job.G) {
+        const uint32_t i = inst_of_chunk(job, g);
+        const Inst &I = inst_at(job, i);
+        const uint64_t c = g - I.chunk_base;
+        const Chunk ch = chunk_geometry(I, c);
+        if (I.model == 1) {
+            cnt = binom(make_stream(I.seed, (uint32_t)c, 0, TAG_CBIN), ch.N, I.p);
+        } else if (I.directed) {
+            cnt = dtree_count(I, c);
+        } else {
+            uint64_t lo = 0, hi = I.P;
+            while (hi - lo > 1) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (uord(I.P, mid) <= c) lo = mid; else hi = mid;
+            }
+            cnt = utree_count(I, lo, lo + (c - uord(I.P, lo)));
+        }
+        T = tiles_of(ch.N, I.s);
+        Us = T ? (1ull << unit_depth(T, job.unit_log)) : 0;
+        job.off[g] = cnt;
+        job.tstart[g] = T;
+        job.ustart[g] = Us;
+    }
+    const uint64_t sc = wave_incl_scan64(cnt), st = wave_incl_scan64(T), su = wave_incl_scan64(Us);
+    if (threadIdx.x == 63) {
+        const uint64_t nb = (job.G + 63) / 64;
+        job.bsum[blockIdx.x] = sc;
+        job.bsum[nb + blockIdx.x] = st;
+        job.bsum[2 * nb + blockIdx.x] = su;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scan, second phase: one workgroup of 1024 lanes turns the wave sums into
+// exclusive prefixes in rounds of 4096 entries (four consecutive entries per
+// lane, coalesced): per-lane sums, wave scans, a scan of the 16 wave totals,
+// a running carry.  The next round's entries are loaded before the current
+// round is scanned.  It also writes the totals and the status words.
+// Third phase (fix_kernel): every chunk adds its wave's prefix to the
+// in-wave prefix of its own values.
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void scan_kernel(Job job)
 {
     __shared__ uint64_t s_wave[3][16];
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint64_t G = job.G;
-    uint64_t *arr[3] = {job.off, job.tstart, job.ustart};
+    const uint64_t G = (job.G + 63) / 64;     // wave sums to scan
+    uint64_t *arr[3] = {job.bsum, job.bsum + G, job.bsum + 2 * G};
     uint64_t carry[3] = {0, 0, 0};
     uint64_t cur[3][4], nxt[3][4];
     auto load = [&](uint64_t base, uint64_t (&dst)[3][4]) {
@@ -180,12 +197,27 @@ __global__ __launch_bounds__(1024) void scan_kernel(Job job)
     }
     if (t == 0) {
         const uint64_t E = carry[0], T = carry[1], U = carry[2];
-        job.off[G] = E; job.tstart[G] = T; job.ustart[G] = U;
+        job.off[job.G] = E; job.tstart[job.G] = T; job.ustart[job.G] = U;
         const uint64_t overflow = (E > job.capacity || T > job.tile_cap) ? 1 : 0;
         job.status[0] = E; job.status[1] = overflow; job.status[2] = T; job.status[3] = U;
         job.status[4] = 0;
         if (T <= job.tile_cap) job.tile_off[T] = E;
         if (job.out_total) *job.out_total = E;
+    }
+}
+
+// Third phase: exclusive offsets of every chunk (one wave per 64 chunks).
+__global__ __launch_bounds__(64) void fix_kernel(Job job)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    const uint64_t nb = (job.G + 63) / 64;
+    const bool in = g < job.G;
+    const uint64_t c = in ? job.off[g] : 0, t = in ? job.tstart[g] : 0, u = in ? job.ustart[g] : 0;
+    const uint64_t sc = wave_incl_scan64(c), st = wave_incl_scan64(t), su = wave_incl_scan64(u);
+    if (in) {
+        job.off[g] = job.bsum[blockIdx.x] + sc - c;
+        job.tstart[g] = job.bsum[nb + blockIdx.x] + st - t;
+        job.ustart[g] = job.bsum[2 * nb + blockIdx.x] + su - u;
     }
 }
 

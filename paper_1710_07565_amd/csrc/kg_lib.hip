@@ -25,6 +25,7 @@ namespace {
 typedef unsigned __int128 u128;
 
 constexpr uint32_t kSpecVersion = 1;
+constexpr uint64_t kMaxChunks = 1ull << 36;   // chunks of one call (a batch: all instances)
 
 // Non-semantic knobs.
 int64_t g_leaf_cap = 0;        // 0: default
@@ -132,7 +133,7 @@ kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
 }
 
 struct Layout {
-    uint64_t status, insts, off, tstart, ustart, tile_off, queue, total;
+    uint64_t status, insts, off, tstart, ustart, bsum, tile_off, queue, total;
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -146,6 +147,7 @@ Layout layout_for(uint32_t ninst, uint64_t G, uint64_t Tb)
     L.off = o; o = align256(o + (G + 1) * 8);
     L.tstart = o; o = align256(o + (G + 1) * 8);
     L.ustart = o; o = align256(o + (G + 1) * 8);
+    L.bsum = o; o = align256(o + 3 * ((G + 63) / 64) * 8);
     L.tile_off = o; o = align256(o + (Tb + 1) * 8);
     L.queue = o; o = align256(o + (Tb + 1) * 8);
     L.total = o;
@@ -171,6 +173,8 @@ kg_status prepare(const kg_instance *in, uint32_t count, Prepared &P)
         P.insts[i].chunk_base = P.G;
         P.G += P.insts[i].nchunks;
         P.Tb += tb;
+        // one-dimensional grids of one wave per 64 chunks
+        if (P.G > kMaxChunks) return KG_ERANGE;
     }
     P.L = layout_for(count, P.G, P.Tb);
     return KG_OK;
@@ -229,6 +233,7 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     job.off = (uint64_t *)(ws.base + P.L.off);
     job.tstart = (uint64_t *)(ws.base + P.L.tstart);
     job.ustart = (uint64_t *)(ws.base + P.L.ustart);
+    job.bsum = (uint64_t *)(ws.base + P.L.bsum);
     job.tile_off = (uint64_t *)(ws.base + P.L.tile_off);
     job.status = (uint64_t *)(ws.base + P.L.status);
     job.queue = (uint64_t *)(ws.base + P.L.queue);
@@ -253,6 +258,7 @@ kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s, bool residen
     {
         KernelTimer tm(KG_KERNEL_SCAN, s);
         hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, job);
+        hipLaunchKernelGGL(fix_kernel, dim3((uint32_t)nb), dim3(64), 0, s, job);
     }
     if (job.inst_off)
         hipLaunchKernelGGL(inst_offsets_kernel, dim3((job.ninst + 1 + 255) / 256), dim3(256), 0, s, job);
