@@ -231,8 +231,10 @@ __global__ __launch_bounds__(256) void inst_offsets_kernel(Job job)
 }
 
 // ---------------------------------------------------------------------------
-// plan: one lane per planner unit (a subtree of <= 64 tiles of one chunk's
-// tile tree, at depth d, index j).  The lane walks from the tile-tree root
+// plan: each lane takes a contiguous range of planner units (a unit is a
+// subtree of <= 64 tiles of one chunk's tile tree, at depth d, index j), so
+// the chunk of its next unit is found by stepping forward.  For each unit
+// the lane walks from the tile-tree root
 // to the unit (the communication-free path: the count of the unit and the
 // counts left of it), then traverses the unit depth first, left child first,
 // so leaves come in tile order and each tile's output offset is a running
@@ -248,9 +250,14 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
     const uint32_t lane = threadIdx.x;
     if (job.status[1]) return;
     const uint64_t U = job.status[3];
+    // blocked unit ranges: a lane's next unit is the following one, so the
+    // chunk index only moves forward (one binary search per lane)
     const uint64_t TL = (uint64_t)gridDim.x * 64;
-    uint64_t u = (uint64_t)blockIdx.x * 64 + lane;
-    bool active = u < U;
+    const uint64_t per = (U + TL - 1) / TL;
+    uint64_t u = ((uint64_t)blockIdx.x * 64 + lane) * per;
+    const uint64_t uend = u + per < U ? u + per : U;
+    bool active = u < uend;
+    uint64_t g = 0;
     // unit state
     uint64_t seed = 0, Nc = 0, tbase = 0, obase = 0, run = 0, j = 0;
     uint32_t c = 0, s = 0, d = 0, lev = 0;
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
     HypRun hr;
     hr.done = true;
     if (active) {
-        const uint64_t g = last_le(job.ustart, job.G, u);
+        g = last_le(job.ustart, job.G, u);
         const Inst &I = inst_at(job, inst_of_chunk(job, g));
         const uint64_t cc = g - I.chunk_base;
         const Chunk ch = chunk_geometry(I, cc);
@@ -284,11 +291,11 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
                     lo = st_lo[sp][lane]; hi = st_hi[sp][lane]; k = st_k[sp][lane]; heap = st_heap[sp][lane];
                     need_node = false;
                 } else {
-                    u += TL;
-                    if (u >= U) {
+                    ++u;
+                    if (u >= uend) {
                         active = false;
                     } else {
-                        const uint64_t g = last_le(job.ustart, job.G, u);
+                        while (job.ustart[g + 1] <= u) ++g;
                         const Inst &I = inst_at(job, inst_of_chunk(job, g));
                         const uint64_t cc = g - I.chunk_base;
                         const Chunk ch = chunk_geometry(I, cc);
