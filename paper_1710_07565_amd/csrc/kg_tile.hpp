@@ -27,19 +27,17 @@ __device__ __forceinline__ uint64_t ld_uni(const uint64_t *p)
     return *(const __attribute__((address_space(4))) uint64_t *)p;
 }
 
-// Consecutive tiles of one wave: the chunk is looked up when a tile leaves
-// the current one, and the decoding constants of a tile are advanced from
-// those of the previous tile of the same chunk.  The tile context (slots,
-// stream, decoder) lives here and is updated in place.
+// The chunk a wave is in: chunk constants, the stream and the decoder of
+// its tiles (enter), the chunk of a tile (locate) and the context of one
+// tile (tile).  The tile kernel advances the decoder from tile to tile itself;
+// the queue kernel places every tile from scratch.
 struct TileWalk {
     uint64_t g, gstart, gend;   // current chunk, its first tile, first tile of the next
     uint64_t N;                 // slots of the chunk
     uint64_t qs;                // 2^s = qs * dv + rs
-    uint64_t prev_tl;
     uint32_t s;                 // tile exponent
     uint32_t row0;              // first row of the chunk (directed) or its row section
     uint32_t rs;
-    bool prev_ok, have;
     TileCtx tc;
 
     __device__ __forceinline__ void enter(const Job &job, uint64_t gg)
@@ -85,27 +83,17 @@ struct TileWalk {
         qs = uni64((1ull << s) / dv);
         rs = uni((uint32_t)((1ull << s) - qs * dv));
         tc.st = Stream{uni((uint32_t)I.seed), uni((uint32_t)(I.seed >> 32)), c, 0, TAG_TLEAF};
-        prev_ok = false;
-        have = true;
     }
 
-    // chunk of tile t: binary search for the first tile of a wave, then a
-    // forward walk (chunks without tiles are stepped over)
+    // the chunk of tile t (last g with tstart[g] <= t), entered
     __device__ __forceinline__ void locate(const Job &job, uint64_t t)
     {
-        if (!have) {
-            uint64_t lo = 0, hi = job.G;
-            while (hi - lo > 1) {
-                const uint64_t mid = (lo + hi) >> 1;
-                if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
-            }
-            enter(job, lo);
-            return;
+        uint64_t lo = 0, hi = job.G;
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
         }
-        if (t < gend) return;
-        uint64_t gg = g + 1;
-        while (ld_uni(job.tstart + gg + 1) <= t) ++gg;
-        enter(job, gg);
+        enter(job, lo);
     }
 
     // slot count, stream counter and decoding constants of tile t (of the
@@ -117,21 +105,12 @@ struct TileWalk {
         const uint64_t lstart = tl << s;
         if (d.type == 2) {
             d.lbase = lstart;
-        } else if (prev_ok && tl == prev_tl + 1) {
-            // next tile of the chunk: advance by 2^s = qs * dv + rs
-            uint32_t w = d.c0 + rs;
-            uint32_t q = (uint32_t)qs;
-            if (w >= d.dv) { w -= d.dv; ++q; }
-            d.c0 = w;
-            d.r0 += q;
         } else {
             const uint64_t q = lstart / d.dv;
             d.c0 = uni((uint32_t)(lstart - q * d.dv));
             d.r0 = uni(row0 + (uint32_t)q);
         }
         d.lbase = uni64(d.lbase);
-        prev_tl = tl;
-        prev_ok = true;
         tc.S = uni64((N - lstart) < (1ull << s) ? (N - lstart) : (1ull << s));
         tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
         tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
@@ -304,10 +283,11 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 // the LDS atomic returned).  An exclusive scan turns the counters into bucket
 // starts; pass 2 places each draw at its bucket start plus its rank; the
 // window passes (8 to 13 keys per lane) then sort inside buckets and count
-// repeats.  While fewer than ke distinct values are
-// seen, J grows by the shortfall (each draw adds at most one new value).
-// Leaves the sorted set in s[0..ke) and returns true, or returns false once
-// J would exceed lim.
+// repeats.  While fewer than ke distinct values are seen, J grows by the
+// shortfall (each draw adds at most one new value).  Leaves the sorted set in
+// s[0..ke) and returns true, or returns false once J would exceed lim (or
+// in the rare cases the queue kernel handles); the counters are zero again
+// whenever it returns.
 constexpr uint32_t kBucketWords = 512;   // one 32-bit counter per bucket
 constexpr uint32_t kWindowPasses = 64;   // bound on window passes per tile
 
@@ -675,8 +655,6 @@ __global__ __launch_bounds__(64) void queue_kernel(Job job)
         const uint64_t o0 = ld_uni(job.tile_off + t);
         const uint64_t k = ld_uni(job.tile_off + t + 1) - o0;
         TileWalk w;
-        w.have = false;
-        w.prev_tl = 0;
         w.locate(job, t);
         w.tile(t);
         TileCtx &tc = w.tc;
