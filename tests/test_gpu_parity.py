@@ -67,6 +67,8 @@ MID = [
     (90, 8000, True, 90), (10**5, 3 * 10**6, False, 100),
     # tiles of 2^32 slots (keys use all 32 bits)
     (2**26, 2**20, False, 256), (2**26, 2**21, True, 64),
+    # more than 4096 wave sums (the offset scan takes several rounds)
+    (2**18 + 1000, 2**20, True, 2**18 + 1000), (2**16, 2**20, False, 730),
 ]
 
 
