@@ -215,6 +215,16 @@ __device__ __forceinline__ void wstore(uint32_t *s, uint32_t p0, const uint32_t 
     for (int i = 0; i < W; ++i) s[p0 + i] = v[i];
 }
 
+// The lane index as a fresh register value: addresses derived from it are
+// formed where they are used instead of being kept (and spilled) across the
+// whole tile loop.
+__device__ __forceinline__ uint32_t lane_here()
+{
+    uint32_t r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(threadIdx.x));
+    return r;
+}
+
 // Lane-to-lane moves of the merge step (wave-wide DPP shifts by one lane);
 // the lane without a source keeps `edge`.
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t x, uint32_t edge)
@@ -240,7 +250,7 @@ template <int W>
 __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &dups)
 {
     constexpr int H = W / 2, U = W - H;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = lane_here();
     const uint32_t p0 = W * lane;
     uint32_t v[W], m[W];
     wload<W>(s, p0, v);
@@ -494,7 +504,7 @@ __device__ __forceinline__ void emit_narrow(const TileCtx &t, const uint32_t *s,
 {
     const DecV d = dec_vregs(t.dec);
     uint2 *out = reinterpret_cast<uint2 *>(t.edges) + t.o0;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = lane_here();
     const uint32_t nfull = n & ~255u;
     // one 64-bit lane pointer advanced per round; the four stores of a round
     // sit at fixed byte offsets from it (0, 512, 1024, 1536)
