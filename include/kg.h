@@ -137,7 +137,7 @@ enum {
     KG_OPT_LEAF_CAP = 1,        /* samples a wave sorts in LDS per pass (128..1024) */
     KG_OPT_SAMPLE_WAVES = 2,    /* resident sampler waves per compute unit (1..32) */
     KG_OPT_PLAN_WAVES = 3,      /* resident tile-planner waves per compute unit (1..64) */
-    KG_OPT_TIME_KERNELS = 4     /* 1: bracket every kernel launch with hipEvents */
+    KG_OPT_TIME_KERNELS = 4     /* 1: bracket every kernel launch with hipEvents (not under capture) */
 };
 kg_status kg_set_option(int option, int64_t value);
 int64_t kg_get_option(int option);
@@ -149,7 +149,7 @@ int64_t kg_get_option(int option);
  * them.  Host only; synchronises with the recorded events. */
 enum {
     KG_KERNEL_COUNT = 0,   /* per-chunk counts */
-    KG_KERNEL_SCAN = 1,    /* offsets */
+    KG_KERNEL_SCAN = 1,    /* offsets (the scan of the wave sums and the fix-up) */
     KG_KERNEL_PLAN = 2,    /* tile plan */
     KG_KERNEL_SAMPLE = 3,  /* common-case tile sampler */
     KG_KERNEL_QUEUE = 4    /* general base case for the tiles the sampler queued */
