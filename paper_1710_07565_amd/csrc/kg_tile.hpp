@@ -317,33 +317,38 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         // below 2^31 every such draw is valid and needs no checks
         const uint32_t nclean = (t.full && t.bits < 32) ? uni(J >> 8) : 0u;
         uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
+        bool hit = false;
         // the draws stay in registers (x[4 e + q] = draw 256 e + 4 lane + q)
         uint32_t x[16], rk[16];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) { x[4 * e + q] = kNone; rk[4 * e + q] = 0; }
-            if ((uint32_t)e < nit) {
-                const uint32_t blk = lane + 64u * e;
+            const uint32_t blk = lane + 64u * e;
+            if ((uint32_t)e < nclean) {
                 const U4 w = t.st.block_uniform_key(blk);     // the tile's key is wave-uniform
+                const uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], 1u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[4 * e + q] = v[q];
+            } else if ((uint32_t)e < nit && 4 * blk < J) {
+                // only the lanes whose block holds draws below J compute it
+                const U4 w = t.st.block_uniform_key(blk);
                 uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
-                if ((uint32_t)e < nclean) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], 1u);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // branch-free: a draw past J or rejected adds 0 and is kept as ~0
-                        const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
-                        coll |= __ballot(ok & (v[q] == kNone));
-                        rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
-                        v[q] = ok ? v[q] : kNone;
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    // a draw past J or rejected adds 0 and is kept as ~0
+                    const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
+                    hit |= ok & (v[q] == kNone);
+                    rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
+                    v[q] = ok ? v[q] : kNone;
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) x[4 * e + q] = v[q];
             }
         }
+        coll = __ballot(hit);
         __syncthreads();
         if (coll) {
             cw[0] = make_uint4(0, 0, 0, 0);
