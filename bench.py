@@ -403,6 +403,73 @@ def run_batch(args):
     }
 
 
+def run_views(args):
+    """The per-PE partition of the headline workload: the views of all P = 256
+    sections of undirected G(n,m), n = 2^26, m = 2^31 (each off-diagonal
+    chunk belongs to two views, so about twice the graph's edges), generated
+    as one kg_batch of 256 view instances per step, seeds 1..3."""
+    import torch
+    import paper_1710_07565_amd as kg
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, m, P = 2**26, 2**31, 256
+    seeds = [1, 2, 3]
+    vsets = [[kg.Instance(n, kg.GNM, False, m, 0.0, sd, P, view=r + 1) for r in range(P)] for sd in seeds]
+    totals = [sum(batch_totals(kg, vs, dev)) for vs in vsets]
+    cap = max(totals)
+    log("bench: %d views per step, %.3g view edges per step (%.3f x the graph)" % (P, totals[0], totals[0] / m))
+    arena = torch.empty((cap, 2), dtype=torch.uint32, device=dev)
+    offs = torch.empty(P + 1, dtype=torch.uint64, device=dev)
+    ws = torch.empty(max(kg.workspace_bytes(vs) for vs in vsets), dtype=torch.uint8, device=dev)
+    for i in range(args.warmup):
+        kg.batch(vsets[i % 3], arena=arena, offsets=offs, workspace=ws)
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
+    kg.kernel_time_read(3)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        kg.batch(vsets[i % 3], arena=arena, offsets=offs, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
+    samp_ms, samp_n = kg.kernel_time_read(3)
+    ms = e0.elapsed_time(e1)
+    E = sum(totals[i % 3] for i in range(args.steps))
+    value = E / (ms * 1e-3)
+    res = {
+        "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
+        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "per-PE views: all 256 sections of undirected G(n,m) n=2^26 m=2^31 "
+                               "(off-diagonal chunks in two views) as one kg_batch",
+                   "n": n, "m": m, "P": P, "seeds": seeds, "view_edges_per_step": totals[0]},
+        "pct_hbm_write_bw": 100.0 * BYTES_PER_EDGE * value / (HBM_PEAK_GBS * 1e9),
+        "roofline": {"bound": "hbm", "achieved": BYTES_PER_EDGE * E / (samp_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": BYTES_PER_EDGE * E / (samp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": ROOFLINE_KERNEL, "avg_launch_ms": samp_ms / max(samp_n, 1)},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's view of a few sections (each PE's work in the paper's run)
+        import time as _t
+        from oracle import kgref
+        I = kgref.inst(n, m=m, directed=False, seed=1, chunks=P)
+        t0, done, cnt = _t.perf_counter(), 0, 0
+        for r in range(0, P, 37):
+            cnt += len(kgref.pe_view(I, r))
+            done += 1
+            if _t.perf_counter() - t0 > args.cpu_seconds:
+                break
+        dt = _t.perf_counter() - t0
+        res["cpu_baseline"] = {"value": cnt / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of %d views (%d edges, %.1f s), one thread" % (done, P, cnt, dt)}
+    else:
+        res["cpu_baseline"] = None
+    return res
+
+
 def run_serve(args):
     """Open-loop Poisson requests, continuous batching under an HBM budget."""
     import torch
@@ -457,7 +524,7 @@ def main():
     ap.add_argument("--workload", default="gnm_undirected_n26_m31", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "views"])
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--arena-gib", type=float, default=96.0)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -503,6 +570,9 @@ def main():
         return
     if args.mode == "serve":
         print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.mode == "views":
+        print(json.dumps(run_views(args)), flush=True)
         return
     desc = WORKLOADS[args.workload]
     res = run_plain(args, desc)

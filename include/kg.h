@@ -61,7 +61,12 @@ typedef struct {
     double p;            /* G(n,p) edge probability in [0, 1] */
     uint64_t seed;
     uint32_t chunks;
-    uint32_t flags;      /* must be 0 */
+    uint32_t flags;      /* 0: the whole graph; r + 1 (r < chunks): only the edges
+                          * incident to section r, the per-PE view of Sec. 4.1
+                          * (directed: row chunk r) and Sec. 4.2 (undirected: the
+                          * chunks (i, r), i < r, and (r, j), j >= r, of the
+                          * chunk matrix), in canonical chunk order and with the
+                          * bytes those chunks have in the whole graph */
 } kg_instance;
 
 /* Spec version of the output bits (changes whenever any output could). */
@@ -105,6 +110,18 @@ kg_status kg_chunk_counts(const kg_instance *inst, uint64_t *d_counts,
 kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
                    uint64_t arena_edges, uint64_t *d_inst_offsets,
                    void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* The per-PE view of one instance (inst->flags must be 0): the edges
+ * incident to section `rank` (< chunks), i.e. what processing element `rank`
+ * of the paper's distributed run generates without communication (Sec. 4.1,
+ * Sec. 4.2 with the chunk row and column of the section; off-diagonal chunks
+ * appear in the views of both their sections).  Byte-identical to the same
+ * chunks of the whole graph.  The edge total, random for G(n,m) as for
+ * G(n,p), is stored at d_total (device, may be NULL); if it exceeds
+ * capacity_edges nothing is written.  Views are also accepted by kg_batch
+ * (flags = rank + 1), e.g. all P views of a graph in one pass. */
+kg_status kg_pe_view(const kg_instance *inst, uint32_t rank, uint32_t *d_edges, uint64_t capacity_edges,
+                     uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes, void *stream);
 
 /* kg_batch in two parts, so that the generating part can be recorded into a
  * HIP graph (stream capture) and replayed.  kg_batch_upload writes the

@@ -169,6 +169,29 @@ def chunk_edges(I, c, Kc=None):
     return out[:r]
 
 
+def view_chunks(I, rank):
+    """Canonical ordinals of the chunks processing element `rank` generates
+    in the paper's distributed run: its row chunk (Sec. 4.1, directed), or the
+    chunk row and column of its section in the upper-triangular chunk matrix
+    (Sec. 4.2, undirected), in row-major order."""
+    P = int(I.P)
+    rank = int(rank)
+    if I.directed:
+        return [rank]
+
+    def first(i):          # ordinal of the diagonal chunk (i, i)
+        return i * P - i * (i - 1) // 2
+
+    return [first(i) + (rank - i) for i in range(rank)] + [first(rank) + (j - rank) for j in range(rank, P)]
+
+
+def pe_view(I, rank):
+    """The edges PE `rank` generates without communication: for each of its
+    chunks the count from the chunk's own root path, then the chunk's edges."""
+    parts = [chunk_edges(I, c, chunk_count_path(I, c)) for c in view_chunks(I, rank)]
+    return np.concatenate(parts) if parts else np.zeros((0, 2), dtype=np.uint32)
+
+
 def generate(I, threads=0, cap=None):
     """Whole edge list as an (E, 2) uint32 array."""
     if cap is None:

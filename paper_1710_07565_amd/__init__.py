@@ -26,10 +26,11 @@ class Instance:
     p: float = 0.0
     seed: int = 1
     chunks: int = 1
+    view: int = 0        # 0: the whole graph; r + 1: the edges incident to section r (per-PE view)
 
     def c(self):
         return KgInstance(int(self.n), int(self.model), int(bool(self.directed)), int(self.m), float(self.p),
-                          int(self.seed) & (2**64 - 1), int(self.chunks), 0)
+                          int(self.seed) & (2**64 - 1), int(self.chunks), int(self.view))
 
 
 def _torch():
@@ -151,10 +152,12 @@ def batch(instances, arena=None, offsets=None, workspace=None, stream=None, devi
     if arena is None:
         total = 0
         for i in instances:
-            if i.model == GNM:
+            if i.model == GNM and not i.view:
                 total += int(i.m)
-            else:
+            elif not i.view:
                 total += gnp_count(i.n, i.p, i.directed, i.seed, i.chunks, stream=stream, device=device)
+            else:
+                total += view_count(i, stream=stream, device=device)
         arena = torch.empty((total, 2), dtype=torch.uint32, device=device)
     if offsets is None:
         offsets = torch.empty(cnt + 1, dtype=torch.uint64, device=arena.device)
@@ -163,6 +166,46 @@ def batch(instances, arena=None, offsets=None, workspace=None, stream=None, devi
                              offsets.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
     _lib.check(st, "kg_batch")
     return arena, offsets
+
+
+def view_count(inst, workspace=None, stream=None, device="cuda"):
+    """Edges of one instance (whole graph or view) from a counting pass
+    (kg_batch with an empty arena; synchronises the stream)."""
+    torch = _torch()
+    offs = torch.empty(2, dtype=torch.uint64, device=device)
+    empty = torch.empty((0, 2), dtype=torch.uint32, device=device)
+    ws, need = _workspace([inst], workspace, device)
+    arr = (KgInstance * 1)(inst.c())
+    _lib.check(_lib.lib().kg_batch(arr, 1, None, 0, offs.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
+               "kg_batch")
+    torch.cuda.current_stream(device).synchronize() if stream is None else stream.synchronize()
+    return int(offs.view(torch.int64)[1].item())
+
+
+def pe_view(n, rank, chunks, directed=True, m=0, p=None, seed=1, out=None, total=None, workspace=None,
+            stream=None, device="cuda"):
+    """The edges incident to section `rank` of the instance (the per-PE view
+    of Sec. 4.1 / 4.2: directed, row chunk `rank`; undirected, the chunk row
+    and column of section `rank` of the chunk matrix), in canonical chunk
+    order; G(n,m) unless p is given.  Without `out` the exact size is found
+    first; with `out`, returns (out, total) as gnp() does."""
+    torch = _torch()
+    model = GNM if p is None else GNP
+    inst = Instance(n, model, directed, m if p is None else 0, 0.0 if p is None else p, seed, chunks)
+    view = Instance(n, model, directed, inst.m, inst.p, seed, chunks, view=int(rank) + 1)
+    sized = out is None
+    if sized:
+        out = torch.empty((view_count(view, workspace=workspace, stream=stream, device=device), 2),
+                          dtype=torch.uint32, device=device)
+    if total is None:
+        total = torch.zeros(1, dtype=torch.uint64, device=out.device)
+    ws, need = _workspace([view], workspace, out.device)
+    st = _lib.lib().kg_pe_view(inst.c(), int(rank), out.data_ptr() if out.numel() else None, out.shape[0],
+                               total.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(st, "kg_pe_view")
+    if sized:
+        return out
+    return out, total
 
 
 def batch_upload(instances, workspace, stream=None):

@@ -465,8 +465,10 @@ struct Inst {
     double p;
     uint64_t seed;
     uint32_t model, directed, P, s;   // s: tile exponent, tiles of 2^s slots
-    uint64_t nchunks;                 // P (directed) or P(P+1)/2
+    uint64_t nchunks;                 // chunks generated: P (directed) or P(P+1)/2; 1 or P for a view
     uint64_t chunk_base;              // first global chunk index of the instance
+    uint32_t view;                    // 0: the whole graph; r + 1: the edges incident to section r
+    uint32_t pad_;
 };
 
 __host__ __device__ __forceinline__ uint64_t section_bound(const Inst &I, uint64_t i)
@@ -487,6 +489,19 @@ struct Chunk {
     uint64_t b, w;    // undirected: column section start / size
     uint32_t diag;    // undirected triangle chunk
 };
+
+// Ordinal (in the instance's canonical chunk order) of the instance's k-th
+// generated chunk.  A view of section r (the per-PE partition of Sec. 4.1
+// and 4.2) generates, directed, row chunk r alone; undirected, the chunks
+// (i, r) for i < r and (r, j) for j >= r of the upper-triangular chunk
+// matrix, in canonical order -- every edge with an endpoint in section r.
+__host__ __device__ __forceinline__ uint64_t chunk_ordinal(const Inst &I, uint64_t k)
+{
+    if (I.view == 0) return k;
+    const uint64_t r = I.view - 1;
+    if (I.directed) return r;
+    return k < r ? uord(I.P, k) + (r - k) : uord(I.P, r) + (k - r);
+}
 
 __device__ __forceinline__ Chunk chunk_geometry(const Inst &I, uint64_t c)
 {

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64) void count_kernel(Job job)
     if (g < job.G) {
         const uint32_t i = inst_of_chunk(job, g);
         const Inst &I = inst_at(job, i);
-        const uint64_t c = g - I.chunk_base;
+        const uint64_t c = chunk_ordinal(I, g - I.chunk_base);
         const Chunk ch = chunk_geometry(I, c);
         if (I.model == 1) {
             cnt = binom(make_stream(I.seed, (uint32_t)c, 0, TAG_CBIN), ch.N, I.p);
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
     if (active) {
         g = last_le(job.ustart, job.G, u);
         const Inst &I = inst_at(job, inst_of_chunk(job, g));
-        const uint64_t cc = g - I.chunk_base;
+        const uint64_t cc = chunk_ordinal(I, g - I.chunk_base);
         const Chunk ch = chunk_geometry(I, cc);
         seed = I.seed; c = (uint32_t)cc; s = I.s; Nc = ch.N;
         const uint64_t units = job.ustart[g + 1] - job.ustart[g];
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
                     } else {
                         while (job.ustart[g + 1] <= u) ++g;
                         const Inst &I = inst_at(job, inst_of_chunk(job, g));
-                        const uint64_t cc = g - I.chunk_base;
+                        const uint64_t cc = chunk_ordinal(I, g - I.chunk_base);
                         const Chunk ch = chunk_geometry(I, cc);
                         seed = I.seed; c = (uint32_t)cc; s = I.s; Nc = ch.N;
                         const uint64_t units = job.ustart[g + 1] - job.ustart[g];

@@ -100,8 +100,9 @@ kg_status ensure_init(int *dev_out)
 // Validation and the per-instance plan.
 kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
 {
-    if (in.flags != 0 || in.model > 1 || in.directed > 1) return KG_EINVAL;
+    if (in.model > 1 || in.directed > 1) return KG_EINVAL;
     if (in.n < 1 || in.chunks < 1 || (uint64_t)in.chunks > in.n) return KG_EINVAL;
+    if (in.flags > in.chunks) return KG_EINVAL;     // 0, or 1 + the section of a view
     if (in.n > (1ull << 32)) return KG_ERANGE;
     const u128 N128 = in.directed ? (u128)in.n * (in.n - 1) : (u128)in.n * (in.n - 1) / 2;
     if (N128 >= ((u128)1 << 53)) return KG_ERANGE;
@@ -126,9 +127,18 @@ kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
     out.directed = in.directed;
     out.P = in.chunks;
     out.s = s;
-    out.nchunks = in.directed ? (uint64_t)in.chunks : (uint64_t)in.chunks * (in.chunks + 1) / 2;
-    // sum over chunks of ceil(N_c / 2^s) <= N / 2^s + chunks
-    tile_bound = (N >> s) + out.nchunks;
+    out.view = in.flags;
+    if (in.flags == 0) {
+        out.nchunks = in.directed ? (uint64_t)in.chunks : (uint64_t)in.chunks * (in.chunks + 1) / 2;
+        // sum over chunks of ceil(N_c / 2^s) <= N / 2^s + chunks
+        tile_bound = (N >> s) + out.nchunks;
+    } else {
+        // the chunks incident to section r hold at most h_r n slots
+        const uint64_t r = in.flags - 1;
+        const uint64_t h = section_bound(out, r + 1) - section_bound(out, r);
+        out.nchunks = in.directed ? 1 : (uint64_t)in.chunks;
+        tile_bound = (uint64_t)(((u128)h * in.n) >> s) + out.nchunks;
+    }
     return KG_OK;
 }
 
@@ -440,6 +450,18 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
     if (!d_arena) arena_edges = 0;
     return run(h_inst, count, d_arena, arena_edges, nullptr, d_inst_offsets, d_workspace, workspace_bytes,
                stream, false, nullptr, nullptr);
+}
+
+kg_status kg_pe_view(const kg_instance *inst, uint32_t rank, uint32_t *d_edges, uint64_t capacity_edges,
+                     uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!inst || inst->flags != 0 || rank >= inst->chunks) return KG_EINVAL;
+    if (((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    kg_instance I = *inst;
+    I.flags = rank + 1;
+    if (!d_edges) capacity_edges = 0;
+    return run(&I, 1, d_edges, capacity_edges, d_total, nullptr, d_workspace, workspace_bytes, stream, false,
+               nullptr, nullptr);
 }
 
 kg_status kg_batch_upload(const kg_instance *h_inst, uint32_t count, void *d_workspace,

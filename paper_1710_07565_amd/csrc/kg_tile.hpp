@@ -50,14 +50,14 @@ struct TileWalk {
         memset(&I, 0, sizeof(I));
         if (job.ninst == 1) {
             I.n = job.one.n; I.seed = job.one.seed; I.chunk_base = job.one.chunk_base;
-            I.directed = job.one.directed; I.P = job.one.P; I.s = job.one.s;
+            I.directed = job.one.directed; I.P = job.one.P; I.s = job.one.s; I.view = job.one.view;
         } else {
             const __attribute__((address_space(4))) Inst *q =
                 (const __attribute__((address_space(4))) Inst *)(job.insts + inst_of_chunk(job, g));
             I.n = q->n; I.seed = q->seed; I.chunk_base = q->chunk_base;
-            I.directed = q->directed; I.P = q->P; I.s = q->s;
+            I.directed = q->directed; I.P = q->P; I.s = q->s; I.view = q->view;
         }
-        const uint32_t c = uni((uint32_t)(g - I.chunk_base));
+        const uint32_t c = uni((uint32_t)chunk_ordinal(I, g - I.chunk_base));
         s = uni(I.s);
         const Chunk ch = chunk_geometry(I, c);
         N = uni64(ch.N);

@@ -61,7 +61,7 @@ def test_workspace_bytes_and_validation(L):
     from paper_1710_07565_amd import _lib
     out = ctypes.c_uint64(0)
     assert L.kg_workspace_bytes(ctypes.byref(_inst()), 1, ctypes.byref(out)) == 0 and out.value > 0
-    bad = [dict(n=0), dict(chunks=0), dict(chunks=101), dict(m=100 * 99 + 1), dict(model=2), dict(flags=1),
+    bad = [dict(n=0), dict(chunks=0), dict(chunks=101), dict(m=100 * 99 + 1), dict(model=2), dict(flags=5),
            dict(model=1, p=1.5), dict(model=1, p=-0.1), dict(model=1, p=float("nan"))]
     for kw in bad:
         assert L.kg_workspace_bytes(ctypes.byref(_inst(**kw)), 1, ctypes.byref(out)) == _lib.KG_EINVAL, kw
@@ -73,6 +73,24 @@ def test_workspace_bytes_and_validation(L):
     assert L.kg_workspace_bytes(ctypes.byref(_inst(n=94906266, m=0, chunks=1)), 1, ctypes.byref(out)) == 0
     assert L.kg_workspace_bytes(ctypes.byref(_inst(n=134217728, directed=0, m=0, chunks=1)), 1,
                                 ctypes.byref(out)) == 0
+
+
+def test_view_flags(L):
+    """flags = r + 1 selects the view of section r (r < chunks); its
+    workspace is that of the chunks incident to the section."""
+    out = ctypes.c_uint64(0)
+    full = ctypes.c_uint64(0)
+    assert L.kg_workspace_bytes(ctypes.byref(_inst(directed=0, chunks=8, m=2000)), 1, ctypes.byref(full)) == 0
+    for r in range(8):
+        assert L.kg_workspace_bytes(ctypes.byref(_inst(directed=0, chunks=8, m=2000, flags=r + 1)), 1,
+                                    ctypes.byref(out)) == 0
+        assert 0 < out.value <= full.value
+    from paper_1710_07565_amd import _lib
+    assert L.kg_workspace_bytes(ctypes.byref(_inst(directed=0, chunks=8, m=2000, flags=9)), 1,
+                                ctypes.byref(out)) == _lib.KG_EINVAL
+    # kg_pe_view refuses a rank outside [0, chunks) or an instance that is already a view
+    assert L.kg_pe_view(ctypes.byref(_inst(chunks=4)), 4, None, 0, None, None, 0, None) == _lib.KG_EINVAL
+    assert L.kg_pe_view(ctypes.byref(_inst(chunks=4, flags=1)), 0, None, 0, None, None, 0, None) == _lib.KG_EINVAL
 
 
 def test_generation_calls_reject_bad_arguments_without_a_device(L):
