@@ -75,7 +75,7 @@ void kgref_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t o
 
 /* Stream tags: every recursion node, chunk and tile owns one stream
  * (Sec. 2.2: one seed per recursion subtree, independent of the PE). */
-enum { TAG_DTREE = 1, TAG_UTREE = 2, TAG_CBIN = 3, TAG_TTREE = 4, TAG_TLEAF = 5, TAG_INST = 6 };
+enum { TAG_DTREE = 1, TAG_UTREE = 2, TAG_CBIN = 3, TAG_TTREE = 4, TAG_TLEAF = 5, TAG_INST = 6, TAG_SKIP = 7 };
 
 /* A stream is Philox keyed by the seed with counter (j, a, b, tag);
  * j counts 128-bit blocks. */
@@ -892,6 +892,116 @@ int64_t kgref_generate(const kgref_inst *I, uint32_t *out, uint64_t cap, int thr
     free(counts);
     free(off);
     return err ? KGREF_EINVAL : (int64_t)total;
+}
+
+/* ------------------------------------------------------------------------
+ * The geometric-skip G(n,p) variant (a second sampler for the same law,
+ * with its own bits).  Every slot is an independent Bernoulli(p) trial
+ * (Sec. 2.1.1, 4.3); instead of a binomial count per chunk and a sample of
+ * that size, each tile of the chunk (the same 2^s-slot tiles) runs the
+ * trials itself by waiting times: the number of failures before the next
+ * success is floor(log U / log(1 - p)) (geometric law), U from the tile's
+ * stream (seed, chunk ordinal, tile, TAG_SKIP), one 64-bit draw per gap.
+ * For p > 1/2 the waiting times are those of the failures (probability
+ * 1 - p) and every other slot is a success.  Keys come out ascending.
+ * ------------------------------------------------------------------------ */
+
+/* Successes of one tile of St slots: their number; the tile-local keys go to
+ * keys[] when keys is not NULL. */
+static uint64_t skip_tile(uint64_t St, double p, uint64_t seed, uint32_t c, uint32_t t, uint64_t *keys)
+{
+    if (!(p > 0.0)) return 0;
+    if (p >= 1.0) {
+        if (keys) for (uint64_t x = 0; x < St; x++) keys[x] = x;
+        return St;
+    }
+    const int flip = p > 0.5;
+    const double L = kgref_log1p(flip ? -(1.0 - p) : -p);
+    stream_t s;
+    stream_init(&s, seed, c, t, TAG_SKIP);
+    uint64_t pos = 0, k = 0;
+    for (;;) {
+        double U = u64_to_unit(stream_u64(&s));
+        double g = floor(kgref_log(U) / L);
+        uint64_t next = g >= (double)(St - pos) ? St : pos + (uint64_t)g;   /* the next trial event, or the end */
+        if (flip) {
+            /* slots pos .. next-1 are successes, next (if inside) a failure */
+            for (uint64_t x = pos; x < next; x++) { if (keys) keys[k] = x; k++; }
+        } else if (next < St) {
+            if (keys) keys[k] = next;
+            k++;
+        }
+        if (next >= St) return k;
+        pos = next + 1;
+    }
+}
+
+static uint64_t skip_chunk(const kgref_inst *I, uint64_t c, uint32_t *out)
+{
+    uint32_t s = kgref_tile_exponent(I);
+    uint64_t Nc = chunk_slots(I, c);
+    uint64_t T = (Nc + ((1ull << s) - 1)) >> s;
+    chunk_geo g;
+    chunk_geometry(I, c, &g);
+    uint64_t o = 0, room = 0;
+    uint64_t *keys = NULL;
+    for (uint64_t t = 0; t < T; t++) {
+        uint64_t St = tile_range_slots(t, t + 1, s, Nc);
+        uint64_t k = skip_tile(St, I->p, I->seed, (uint32_t)c, (uint32_t)t, NULL);
+        if (out && k > 0) {
+            if (k > room) {
+                free(keys);
+                room = k;
+                keys = (uint64_t *)malloc(room * sizeof(uint64_t));
+            }
+            skip_tile(St, I->p, I->seed, (uint32_t)c, (uint32_t)t, keys);
+            for (uint64_t e = 0; e < k; e++) {
+                uint32_t u, v;
+                decode(&g, (t << s) + keys[e], &u, &v);
+                out[2 * (o + e)] = u;
+                out[2 * (o + e) + 1] = v;
+            }
+        }
+        o += k;
+    }
+    free(keys);
+    return o;
+}
+
+/* Edges of chunk c under the skip variant (out may be NULL: count only). */
+int64_t kgref_skip_chunk_edges(const kgref_inst *I, uint64_t c, uint32_t *out)
+{
+    int st = kgref_validate(I);
+    if (st) return st;
+    if (I->model != 1) return KGREF_EINVAL;
+    return (int64_t)skip_chunk(I, c, out);
+}
+
+/* Whole edge list under the skip variant, chunks in canonical order; returns
+ * the number of edges (KGREF_ENOSPC if above cap: nothing written). */
+int64_t kgref_skip_generate(const kgref_inst *I, uint32_t *out, uint64_t cap, int threads)
+{
+    int st = kgref_validate(I);
+    if (st) return st;
+    if (I->model != 1) return KGREF_EINVAL;
+    uint64_t C = kgref_num_chunks(I);
+    uint64_t *off = (uint64_t *)malloc((C + 1) * sizeof(uint64_t));
+    off[0] = 0;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t c = 0; c < (int64_t)C; c++) off[c + 1] = skip_chunk(I, (uint64_t)c, NULL);
+    for (uint64_t c = 0; c < C; c++) off[c + 1] += off[c];
+    uint64_t total = off[C];
+    if (total > cap) { free(off); return KGREF_ENOSPC; }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t c = 0; c < (int64_t)C; c++) skip_chunk(I, (uint64_t)c, out + 2 * off[c]);
+    (void)threads;
+    free(off);
+    return (int64_t)total;
 }
 
 /* Per-instance seed of a batch: the Philox image of (0, i, 0, INST) under the

@@ -67,6 +67,8 @@ def lib():
         L.kgref_chunk_edges_given.argtypes = [ip, u64, u64, vp]
         L.kgref_chunk_edges_given.restype = ctypes.c_int64
         L.kgref_generate.argtypes = [ip, vp, u64, ctypes.c_int]; L.kgref_generate.restype = ctypes.c_int64
+        L.kgref_skip_chunk_edges.argtypes = [ip, u64, vp]; L.kgref_skip_chunk_edges.restype = ctypes.c_int64
+        L.kgref_skip_generate.argtypes = [ip, vp, u64, ctypes.c_int]; L.kgref_skip_generate.restype = ctypes.c_int64
         L.kgref_instance_seed.argtypes = [u64, u32]; L.kgref_instance_seed.restype = u64
         L.kgref_max_threads.argtypes = []; L.kgref_max_threads.restype = ctypes.c_int
         L.kgref_eval_many.argtypes = [ctypes.c_int, vp, vp, u64]; L.kgref_eval_many.restype = None
@@ -190,6 +192,26 @@ def pe_view(I, rank):
     chunks the count from the chunk's own root path, then the chunk's edges."""
     parts = [chunk_edges(I, c, chunk_count_path(I, c)) for c in view_chunks(I, rank)]
     return np.concatenate(parts) if parts else np.zeros((0, 2), dtype=np.uint32)
+
+
+def skip_chunk_edges(I, c):
+    """Edges of chunk c under the geometric-skip G(n,p) variant."""
+    k = lib().kgref_skip_chunk_edges(ctypes.byref(I), int(c), None)
+    if k < 0:
+        raise ValueError("kgref_skip_chunk_edges status %d" % k)
+    out = np.zeros((max(k, 1), 2), dtype=np.uint32)
+    lib().kgref_skip_chunk_edges(ctypes.byref(I), int(c), _ptr(out))
+    return out[:k]
+
+
+def skip_generate(I, threads=0):
+    """Whole edge list under the geometric-skip G(n,p) variant."""
+    total = sum(int(lib().kgref_skip_chunk_edges(ctypes.byref(I), c, None)) for c in range(num_chunks(I)))
+    out = np.zeros((max(total, 1), 2), dtype=np.uint32)
+    r = lib().kgref_skip_generate(ctypes.byref(I), _ptr(out), total, int(threads))
+    if r < 0:
+        raise ValueError("kgref_skip_generate status %d" % r)
+    return out[:r]
 
 
 def generate(I, threads=0, cap=None):
