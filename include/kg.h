@@ -111,6 +111,18 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
                    uint64_t arena_edges, uint64_t *d_inst_offsets,
                    void *d_workspace, uint64_t workspace_bytes, void *stream);
 
+/* G(n,p) by geometric skips, a second sampler for the same law with its own
+ * bits (Sec. 2.1.1, 4.3): each 2^s-slot tile of each chunk runs its Bernoulli
+ * trials by waiting times, floor(log U / log(1 - p)) failures before the next
+ * success (for p > 1/2: the waiting times of the failures), one 64-bit draw
+ * of Philox counter (draw/2, chunk ordinal, tile, 7) per gap; a count pass,
+ * a scan of the tile counts and a write pass.  Output order and arguments as
+ * kg_gnp: the total goes to d_total (device, may be NULL); if it exceeds
+ * capacity_edges nothing is written. */
+kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks,
+                      uint32_t *d_edges, uint64_t capacity_edges, uint64_t *d_total,
+                      void *d_workspace, uint64_t workspace_bytes, void *stream);
+
 /* The per-PE view of one instance (inst->flags must be 0): the edges
  * incident to section `rank` (< chunks), i.e. what processing element `rank`
  * of the paper's distributed run generates without communication (Sec. 4.1,

@@ -208,6 +208,32 @@ def pe_view(n, rank, chunks, directed=True, m=0, p=None, seed=1, out=None, total
     return out, total
 
 
+def gnp_skip(n, p, directed=True, seed=1, chunks=1, out=None, total=None, workspace=None, stream=None,
+             device="cuda"):
+    """G(n,p) by geometric skips per tile (kg_gnp_skip): the same law as
+    gnp(), other bits.  Without `out` a first call finds the size; with
+    `out`, returns (out, total) as gnp() does."""
+    torch = _torch()
+    inst = Instance(n, GNP, directed, 0, p, seed, chunks)
+    ws, need = _workspace([inst], workspace, device if out is None else out.device)
+    if total is None:
+        total = torch.zeros(1, dtype=torch.uint64, device=ws.device)
+    sized = out is None
+    if sized:
+        st = _lib.lib().kg_gnp_skip(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
+                                    None, 0, total.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+        _lib.check(st, "kg_gnp_skip")
+        E = int(total.view(torch.int64).cpu()[0])
+        out = torch.empty((E, 2), dtype=torch.uint32, device=ws.device)
+    st = _lib.lib().kg_gnp_skip(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
+                                out.data_ptr() if out.numel() else None, out.shape[0], total.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(st, "kg_gnp_skip")
+    if sized:
+        return out
+    return out, total
+
+
 def batch_upload(instances, workspace, stream=None):
     """Write the descriptor table of `instances` into `workspace` (a device
     uint8 tensor of at least workspace_bytes(instances)); synchronises."""

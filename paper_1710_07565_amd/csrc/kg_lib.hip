@@ -13,6 +13,7 @@
 
 #include "../../include/kg.h"
 #include "kg_tile.hpp"
+#include "kg_skip.hpp"
 
 namespace kg {
 __device__ double g_lnf_tab[kLnfTab + 1];
@@ -462,6 +463,50 @@ kg_status kg_pe_view(const kg_instance *inst, uint32_t rank, uint32_t *d_edges, 
     if (!d_edges) capacity_edges = 0;
     return run(&I, 1, d_edges, capacity_edges, d_total, nullptr, d_workspace, workspace_bytes, stream, false,
                nullptr, nullptr);
+}
+
+kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks, uint32_t *d_edges,
+                      uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
+                      void *stream)
+{
+    const kg_instance I = make_inst(n, KG_GNP, directed, 0, p, seed, chunks);
+    if (((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    if (!d_edges) capacity_edges = 0;
+    Prepared P;
+    kg_status st = prepare(&I, 1, P);
+    if (st) return st;
+    const uint64_t nw = (P.Tb + 63) / 64;          // one wave per 64 tiles
+    if (nw > 0x7FFFFFFFull || nw > P.Tb + 1) return KG_ERANGE;
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s) && !d_workspace) return KG_EINVAL;
+    int dev = 0;
+    st = ensure_init(&dev);
+    if (st) return st;
+    Workspace ws;
+    st = acquire(ws, d_workspace, workspace_bytes, P.L.total, s);
+    if (st) return st;
+    // the chunk and tile layout from the main path's count and offset
+    // kernels; their binomial total is not this sampler's, so no capacity
+    // check and no total there
+    Job job = make_job(P, ws, d_edges, ~0ull);
+    st = launch_counts(P, job, s, false);
+    if (!st) {
+        {
+            KernelTimer tm(KG_KERNEL_PLAN, s);
+            hipLaunchKernelGGL(skip_count_kernel, dim3((uint32_t)nw), dim3(64), 0, s, job);
+        }
+        Job jw = job;
+        jw.capacity = capacity_edges;
+        jw.out_total = d_total;
+        hipLaunchKernelGGL(skip_scan_kernel, dim3(1), dim3(1024), 0, s, jw, nw);
+        {
+            KernelTimer tm(KG_KERNEL_SAMPLE, s);
+            hipLaunchKernelGGL(skip_write_kernel, dim3((uint32_t)nw), dim3(64), 0, s, jw);
+        }
+        if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+    }
+    release(ws, s);
+    return st;
 }
 
 kg_status kg_batch_upload(const kg_instance *h_inst, uint32_t count, void *d_workspace,
