@@ -119,3 +119,12 @@ def test_oracle_tile_exponent_is_minimal(kgref):
         N = n * (n - 1)
         assert (m << s) >= 362 * N or s == 32
         assert s == 9 or (m << (s - 1)) < 362 * N
+
+
+def test_skip_variant_argument_checks(L):
+    """kg_gnp_skip refuses bad arguments before touching the device."""
+    from paper_1710_07565_amd import _lib
+    assert L.kg_gnp_skip(100, 1.5, 1, 1, 4, None, 0, None, None, 0, None) == _lib.KG_EINVAL
+    assert L.kg_gnp_skip(100, 0.1, 1, 1, 0, None, 0, None, None, 0, None) == _lib.KG_EINVAL
+    assert L.kg_gnp_skip(100, 0.1, 1, 1, 4, 4, 10, None, None, 0, None) == _lib.KG_EINVAL   # misaligned
+    assert L.kg_gnp_skip(2**33, 0.1, 1, 1, 4, None, 0, None, None, 0, None) == _lib.KG_ERANGE
