@@ -147,7 +147,25 @@ __global__ __launch_bounds__(64) void skip_write_kernel(Job job)
     const SkipTile r = skip_tile_at(job, t);
     uint2 *out = reinterpret_cast<uint2 *>(job.edges) + o;
     uint64_t e = 0;
-    skip_trials(r.st, r.S, r.I.p, [&](uint64_t x) { out[e++] = skip_decode(r.I, r.ch, r.lbase + x); });
+    if (r.ch.diag) {
+        skip_trials(r.st, r.S, r.I.p, [&](uint64_t x) { out[e++] = skip_decode(r.I, r.ch, r.lbase + x); });
+        return;
+    }
+    // directed rows and rectangles: keys ascend, so the row and column of a
+    // key follow from the previous ones by adding the gap (a division only
+    // when the gap spans a whole row)
+    const uint64_t W = r.I.directed ? r.I.n - 1 : r.ch.w;
+    const uint64_t first = r.I.directed ? r.ch.row0 * W + r.lbase : r.lbase;
+    uint64_t row = first / W, col = first % W, last = 0;
+    skip_trials(r.st, r.S, r.I.p, [&](uint64_t x) {
+        const uint64_t gap = x - last;
+        last = x;
+        if (gap >= W) { row += gap / W; col += gap % W; }
+        else col += gap;
+        if (col >= W) { col -= W; ++row; }
+        out[e++] = r.I.directed ? make_uint2((uint32_t)row, (uint32_t)(col + (col >= row)))
+                                : make_uint2((uint32_t)(r.ch.a + row), (uint32_t)(r.ch.b + col));
+    });
 }
 
 }  // namespace kg
