@@ -1093,3 +1093,180 @@ int64_t kgref_generate_chunks(const kgref_inst *I, const uint64_t *counts, uint6
     free(off);
     return err ? KGREF_EINVAL : (int64_t)total;
 }
+
+/* ------------------------------------------------------------------ */
+/* Random geometric graphs in two dimensions (Sec. 2.1.2 model; Sec. 5 */
+/* generator: grid of cells of side >= r, a divide-and-conquer count   */
+/* of the points per sub-square by binomial variates keyed by the      */
+/* subtree, points per cell from the cell's own stream, edges between  */
+/* a cell and its neighbours, each pair tested once).                  */
+/*                                                                     */
+/* Our reading: the unit square is split recursively into quadrants   */
+/* down to 4^L cells of side 2^-L, L the largest level with            */
+/* 2^L r <= 1 and 4^L <= n (cells of side >= max(r, n^-1/2), Sec. 5),  */
+/* at most KGREF_RGG_MAX_LEVEL.  A node at level l, Morton index z,    */
+/* holding k points splits them as: lower half (y) Bin(k, 1/2), its    */
+/* left quadrant Bin(lower, 1/2), the upper-left quadrant              */
+/* Bin(k - lower, 1/2); every probability is exactly 1/2, so the four  */
+/* counts are multinomial(k; 1/4 each) with no rounding of the law.    */
+/* Streams: (seed; j, z, 3 l + slot, TAG_RTREE) for the three draws,   */
+/* (seed; j, cell, 0, TAG_RPTS) for the points, block j = point j.     */
+/* Vertex ids follow the cells in Morton order; edges are the pairs    */
+/* u < v with dx^2 + dy^2 < r^2 (binary64, each operation rounded),    */
+/* listed in ascending (u, v).                                         */
+/* ------------------------------------------------------------------ */
+#define TAG_RTREE 8
+#define TAG_RPTS 9
+#define KGREF_RGG_MAX_LEVEL 14
+
+uint32_t kgref_rgg_level(uint64_t n, double r)
+{
+    uint32_t L = 0;
+    while (L < KGREF_RGG_MAX_LEVEL && ldexp(r, (int)L + 1) <= 1.0 && ((uint64_t)1 << (2 * (L + 1))) <= n) L++;
+    return L;
+}
+
+/* the three binomial draws of node (l, z) holding k points -> the four
+ * quadrant counts in Morton order (x bit low, y bit high) */
+static void rgg_split(uint64_t seed, uint32_t l, uint64_t z, uint64_t k, uint64_t q[4])
+{
+    uint64_t lower = kgref_bin(k, 0.5, seed, (uint32_t)z, 3 * l + 0, TAG_RTREE);
+    uint64_t ll = kgref_bin(lower, 0.5, seed, (uint32_t)z, 3 * l + 1, TAG_RTREE);
+    uint64_t ul = kgref_bin(k - lower, 0.5, seed, (uint32_t)z, 3 * l + 2, TAG_RTREE);
+    q[0] = ll;
+    q[1] = lower - ll;
+    q[2] = ul;
+    q[3] = k - lower - ul;
+}
+
+static void rgg_tree(uint64_t seed, uint32_t L, uint32_t l, uint64_t z, uint64_t k, uint64_t *cells)
+{
+    if (l == L) { cells[z] = k; return; }
+    uint64_t q[4];
+    rgg_split(seed, l, z, k, q);
+    for (int i = 0; i < 4; i++) rgg_tree(seed, L, l + 1, 4 * z + (uint64_t)i, q[i], cells);
+}
+
+/* Point counts of all 4^L cells, Morton order. */
+int kgref_rgg_cells(uint64_t n, double r, uint64_t seed, uint64_t *cells)
+{
+    uint32_t L = kgref_rgg_level(n, r);
+    rgg_tree(seed, L, 0, 0, n, cells);
+    return (int)L;
+}
+
+/* One cell's count by walking only its root path, as a processor that owns
+ * the cell (or needs it as a neighbour) does without communication. */
+uint64_t kgref_rgg_cell_count_path(uint64_t n, double r, uint64_t seed, uint64_t cell)
+{
+    uint32_t L = kgref_rgg_level(n, r);
+    uint64_t k = n, z = 0;
+    for (uint32_t l = 0; l < L; l++) {
+        uint64_t q[4];
+        rgg_split(seed, l, z, k, q);
+        uint64_t d = (cell >> (2 * (L - 1 - l))) & 3;
+        z = 4 * z + d;
+        k = q[d];
+    }
+    return k;
+}
+
+static void rgg_cell_xy(uint64_t z, uint32_t L, uint64_t *cx, uint64_t *cy)
+{
+    uint64_t x = 0, y = 0;
+    for (uint32_t i = 0; i < L; i++) {
+        x |= ((z >> (2 * i)) & 1) << i;
+        y |= ((z >> (2 * i + 1)) & 1) << i;
+    }
+    *cx = x;
+    *cy = y;
+}
+
+static uint64_t rgg_morton(uint64_t x, uint64_t y, uint32_t L)
+{
+    uint64_t z = 0;
+    for (uint32_t i = 0; i < L; i++) z |= (((x >> i) & 1) << (2 * i)) | (((y >> i) & 1) << (2 * i + 1));
+    return z;
+}
+
+/* Point j of cell z: (cx + U, cy + V) 2^-L, U and V the two uniforms of
+ * block j of the cell's stream. */
+static void rgg_point(uint64_t seed, uint32_t L, uint64_t z, uint64_t j, double *x, double *y)
+{
+    stream_t s;
+    stream_init(&s, seed, (uint32_t)z, 0, TAG_RPTS);
+    uint32_t w[4];
+    stream_block(&s, j, w);
+    double U = u64_to_unit(((uint64_t)w[1] << 32) | w[0]);
+    double V = u64_to_unit(((uint64_t)w[3] << 32) | w[2]);
+    uint64_t cx, cy;
+    rgg_cell_xy(z, L, &cx, &cy);
+    double h = ldexp(1.0, -(int)L);
+    *x = ((double)cx + U) * h;
+    *y = ((double)cy + V) * h;
+}
+
+static int rgg_adjacent(const double *a, const double *b, double r2)
+{
+    double dx = a[0] - b[0];
+    double dy = a[1] - b[1];
+    return dx * dx + dy * dy < r2;
+}
+
+static int cmp_u64r(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+/* The whole graph: points (2n doubles, vertex order) and the edges in
+ * ascending (u, v), at most cap of them written.  Returns the edge count
+ * (which may exceed cap: then only the first cap are written), or a
+ * negative status. */
+int64_t kgref_rgg2d(uint64_t n, double r, uint64_t seed, double *pts, uint32_t *edges, uint64_t cap)
+{
+    if (!(r >= 0.0) || n > 0xFFFFFFFFull) return KGREF_EINVAL;
+    uint32_t L = kgref_rgg_level(n, r);
+    uint64_t G = (uint64_t)1 << L, C = G * G;
+    uint64_t *cells = (uint64_t *)calloc(C, sizeof(uint64_t));
+    uint64_t *off = (uint64_t *)malloc((C + 1) * sizeof(uint64_t));
+    double *P = pts ? pts : (double *)malloc((2 * n + 2) * sizeof(double));
+    rgg_tree(seed, L, 0, 0, n, cells);
+    off[0] = 0;
+    for (uint64_t z = 0; z < C; z++) off[z + 1] = off[z] + cells[z];
+    for (uint64_t z = 0; z < C; z++)
+        for (uint64_t j = 0; j < cells[z]; j++) rgg_point(seed, L, z, j, &P[2 * (off[z] + j)], &P[2 * (off[z] + j) + 1]);
+    const double r2 = r * r;
+    uint64_t E = 0;
+    for (uint64_t z = 0; z < C; z++) {
+        uint64_t cx, cy, nb[9];
+        int nn = 0;
+        rgg_cell_xy(z, L, &cx, &cy);
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int64_t x = (int64_t)cx + dx, y = (int64_t)cy + dy;
+                if (x < 0 || y < 0 || x >= (int64_t)G || y >= (int64_t)G) continue;
+                uint64_t zz = rgg_morton((uint64_t)x, (uint64_t)y, L);
+                if (zz >= z) nb[nn++] = zz;
+            }
+        qsort(nb, (size_t)nn, sizeof(uint64_t), cmp_u64r);
+        for (uint64_t a = off[z]; a < off[z + 1]; a++)
+            for (int i = 0; i < nn; i++)
+                for (uint64_t b = off[nb[i]]; b < off[nb[i] + 1]; b++) {
+                    if (b <= a || !rgg_adjacent(&P[2 * a], &P[2 * b], r2)) continue;
+                    if (edges && E < cap) { edges[2 * E] = (uint32_t)a; edges[2 * E + 1] = (uint32_t)b; }
+                    E++;
+                }
+    }
+    free(cells);
+    free(off);
+    if (!pts) free(P);
+    return (int64_t)E;
+}
+
+/* The k points of cell z (2k doubles), as the whole generator makes them. */
+void kgref_rgg_cell_points(uint64_t n, double r, uint64_t seed, uint64_t z, uint64_t k, double *out)
+{
+    uint32_t L = kgref_rgg_level(n, r);
+    for (uint64_t j = 0; j < k; j++) rgg_point(seed, L, z, j, &out[2 * j], &out[2 * j + 1]);
+}

@@ -17,6 +17,8 @@ LIB = os.path.join(HERE, "libkgref.so")
 
 GNM, GNP = 0, 1
 TAG_DTREE, TAG_UTREE, TAG_CBIN, TAG_TTREE, TAG_TLEAF, TAG_INST = 1, 2, 3, 4, 5, 6
+TAG_RTREE, TAG_RPTS = 8, 9
+RGG_MAX_LEVEL = 14
 
 
 def build(force=False):
@@ -74,6 +76,12 @@ def lib():
         L.kgref_eval_many.argtypes = [ctypes.c_int, vp, vp, u64]; L.kgref_eval_many.restype = None
         L.kgref_generate_chunks.argtypes = [ip, vp, u64, u64, vp, u64, ctypes.c_int]
         L.kgref_generate_chunks.restype = ctypes.c_int64
+        L.kgref_rgg_level.argtypes = [u64, dbl]; L.kgref_rgg_level.restype = u32
+        L.kgref_rgg_cells.argtypes = [u64, dbl, u64, vp]; L.kgref_rgg_cells.restype = ctypes.c_int
+        L.kgref_rgg_cell_count_path.argtypes = [u64, dbl, u64, u64]
+        L.kgref_rgg_cell_count_path.restype = u64
+        L.kgref_rgg2d.argtypes = [u64, dbl, u64, vp, vp, u64]; L.kgref_rgg2d.restype = ctypes.c_int64
+        L.kgref_rgg_cell_points.argtypes = [u64, dbl, u64, u64, u64, vp]; L.kgref_rgg_cell_points.restype = None
         _lib = L
     return _lib
 
@@ -262,3 +270,47 @@ def generate_chunks(I, counts, c0, c1, out=None, threads=0):
     if r < 0:
         raise ValueError("kgref_generate_chunks status %d" % r)
     return out[:r]
+
+
+# ---------------------------------------------------------------------------
+# Random geometric graphs in two dimensions (Sec. 2.1.2, Sec. 5)
+# ---------------------------------------------------------------------------
+def rgg_level(n, r):
+    """Cells per side 2^L: the largest L <= RGG_MAX_LEVEL with 2^L r <= 1 and
+    4^L <= n (cells of side >= max(r, n^-1/2), Sec. 5)."""
+    return int(lib().kgref_rgg_level(int(n), float(r)))
+
+
+def rgg_cells(n, r, seed):
+    """Point count of every cell, Morton order (the quadrant recursion of
+    Sec. 5.1 down to the cells)."""
+    L = rgg_level(n, r)
+    out = np.zeros(1 << (2 * L), dtype=np.uint64)
+    lib().kgref_rgg_cells(int(n), float(r), int(seed) & (2**64 - 1), _ptr(out))
+    return out
+
+
+def rgg_cell_count_path(n, r, seed, cell):
+    """One cell's count from its root path alone (what a processor owning or
+    bordering the cell recomputes, Sec. 5.1)."""
+    return int(lib().kgref_rgg_cell_count_path(int(n), float(r), int(seed) & (2**64 - 1), int(cell)))
+
+
+def rgg_cell_points(n, r, seed, cell, k):
+    """The k points of one cell, (k, 2) float64."""
+    out = np.zeros((max(int(k), 1), 2), dtype=np.float64)
+    lib().kgref_rgg_cell_points(int(n), float(r), int(seed) & (2**64 - 1), int(cell), int(k), _ptr(out))
+    return out[:int(k)]
+
+
+def rgg2d(n, r, seed):
+    """(points (n, 2) float64 in vertex order, edges (E, 2) uint32 ascending)."""
+    seed = int(seed) & (2**64 - 1)
+    pts = np.zeros((max(int(n), 1), 2), dtype=np.float64)
+    E = lib().kgref_rgg2d(int(n), float(r), seed, _ptr(pts), None, 0)
+    if E < 0:
+        raise ValueError("kgref_rgg2d status %d" % E)
+    out = np.zeros((max(E, 1), 2), dtype=np.uint32)
+    E2 = lib().kgref_rgg2d(int(n), float(r), seed, _ptr(pts), _ptr(out), E)
+    assert E2 == E
+    return pts[:int(n)], out[:E]
