@@ -13,6 +13,7 @@ bounded sample of the same workload on this host (cpu_baseline).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -545,6 +546,86 @@ def run_skip(args):
     return res
 
 
+def run_rgg(args):
+    """Two-dimensional random geometric graph (Sec. 5): n = 2^26 points,
+    r = 0.55 sqrt(ln n / n) (the radius of the paper's RGG experiments),
+    seeds 1..3; points and edges written to HBM every step."""
+    import torch
+    import paper_1710_07565_amd as kg
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n = 2**26
+    r = 0.55 * math.sqrt(math.log(n) / n)
+    seeds = [1, 2, 3]
+    ws = torch.empty(kg.rgg2d_workspace_bytes(n, r), dtype=torch.uint8, device=dev)
+    pts = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    tot = torch.zeros(1, dtype=torch.uint64, device=dev)
+    E = []
+    for sd in seeds:
+        kg.rgg2d(n, r, sd, points=pts, out=torch.empty((0, 2), dtype=torch.uint32, device=dev), total=tot,
+                 workspace=ws)
+        E.append(int(tot.view(torch.int64).cpu()[0]))
+    out = torch.empty((max(E), 2), dtype=torch.uint32, device=dev)
+
+    def step(i):
+        kg.rgg2d(n, r, seeds[i % 3], points=pts, out=out, total=tot, workspace=ws)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
+    for k in range(5):
+        kg.kernel_time_read(k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        step(i)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    per = {}
+    for k, name in enumerate(["tree", "scans", "edge_count_pass", "edge_write_pass", "points"]):
+        t, c = kg.kernel_time_read(k)
+        per[name] = t / max(c, 1) if name != "scans" else t / max(args.steps, 1)
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
+    Etot = sum(E[i % 3] for i in range(args.steps))
+    value = Etot / (ms * 1e-3)
+    bytes_step = [BYTES_PER_EDGE * E[i % 3] + 16 * n for i in range(args.steps)]
+    wr_ms = per["edge_write_pass"]
+    wr_bytes = BYTES_PER_EDGE * Etot / args.steps
+    res = {
+        "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
+        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+u32", "data": "synthetic",
+        "config": {"workload": "2D random geometric graph n=2^26 r=0.55 sqrt(ln n/n) (4^11 cells)",
+                   "n": n, "r": r, "seeds": seeds, "edges_per_step": E[0]},
+        "pct_hbm_write_bw": 100.0 * sum(bytes_step) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "per_launch_ms": per,
+        "roofline": {"bound": "hbm",
+                     "limited_by": "per-vertex distance tests (FP64, neighbour points from L2), two passes",
+                     "kernel": "rgg_edges_kernel<true>", "avg_launch_ms": wr_ms,
+                     "achieved": wr_bytes / (wr_ms * 1e-3) / 1e9, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                     "frac": wr_bytes / (wr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import time as _t
+        from oracle import kgref
+        # a bounded sample: the whole oracle on a 2^22-point instance of the
+        # same recipe (one thread)
+        ns = 2**22
+        rs = 0.55 * math.sqrt(math.log(ns) / ns)
+        t0 = _t.perf_counter()
+        _, Es = kgref.rgg2d(ns, rs, 1)
+        dt = _t.perf_counter() - t0
+        res["cpu_baseline"] = {"value": len(Es) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                               "sample": "n=2^22, r=0.55 sqrt(ln n/n), seed 1: %d edges in %.1f s, one thread"
+                               % (len(Es), dt)}
+    else:
+        res["cpu_baseline"] = None
+    return res
+
+
 def run_serve(args):
     """Open-loop Poisson requests, continuous batching under an HBM budget."""
     import torch
@@ -599,7 +680,7 @@ def main():
     ap.add_argument("--workload", default="gnm_undirected_n26_m31", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "views", "skip"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "views", "skip", "rgg"])
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--arena-gib", type=float, default=96.0)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -651,6 +732,9 @@ def main():
         return
     if args.mode == "skip":
         print(json.dumps(run_skip(args)), flush=True)
+        return
+    if args.mode == "rgg":
+        print(json.dumps(run_rgg(args)), flush=True)
         return
     desc = WORKLOADS[args.workload]
     res = run_plain(args, desc)

@@ -135,6 +135,33 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
 kg_status kg_pe_view(const kg_instance *inst, uint32_t rank, uint32_t *d_edges, uint64_t capacity_edges,
                      uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes, void *stream);
 
+/* Two-dimensional random geometric graph (Sec. 2.1.2 model, Sec. 5
+ * generator): n points uniform in [0,1)^2 and an edge between every two
+ * points at distance below r.  The square is cut into 4^L cells of side
+ * 2^-L, L the largest level <= 14 with 2^L r <= 1 and 4^L <= n (cells of
+ * side >= max(r, n^-1/2), Sec. 5); the points per cell come from a
+ * quadrant recursion of three Bin(k, 1/2) variates per node, keyed by the
+ * node (Philox counter (j, Morton index, 3 level + slot, 8), Sec. 5.1); the
+ * points of a cell from counter (j, cell, 0, 9); the edges from a count
+ * pass, a scan and a write pass over each point's cell and its eight
+ * neighbours (Sec. 5.3).  The output does not depend on any launch setting.
+ *   d_points  device, n x (double x, double y), 16-byte aligned, written in
+ *             vertex order: cells in Morton order (x bit low), then the
+ *             cell's points.  May be NULL only if n == 0.
+ *   d_edges   device, capacity_edges x (uint32 u, uint32 v), u < v, in
+ *             ascending (u, v); (x_u - x_v)^2 + (y_u - y_v)^2 < r^2 in
+ *             binary64 with every operation rounded.  Nothing is written
+ *             if the total exceeds capacity_edges.
+ *   d_total   device uint64, may be NULL: the edge total.
+ * n < 2^32, r >= 0 (KG_EINVAL for NaN or negative r); KG_ERANGE if
+ * n^2 / 4^L > 2^36 (points per cell too many for the per-point pass: r > 1/2
+ * with large n).  Asynchronous on `stream`; the workspace (or, if d_workspace
+ * is NULL, a stream-ordered allocation) holds kg_rgg2d_workspace_bytes. */
+kg_status kg_rgg2d_workspace_bytes(uint64_t n, double r, uint64_t *bytes);
+kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32_t *d_edges,
+                   uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
+                   void *stream);
+
 /* kg_batch in two parts, so that the generating part can be recorded into a
  * HIP graph (stream capture) and replayed.  kg_batch_upload writes the
  * descriptor table of the list into d_workspace (required, at least
@@ -177,11 +204,11 @@ int64_t kg_get_option(int option);
  * returns the summed milliseconds and the number of launches, and forgets
  * them.  Host only; synchronises with the recorded events. */
 enum {
-    KG_KERNEL_COUNT = 0,   /* per-chunk counts */
-    KG_KERNEL_SCAN = 1,    /* offsets (the scan of the wave sums and the fix-up) */
-    KG_KERNEL_PLAN = 2,    /* tile plan */
-    KG_KERNEL_SAMPLE = 3,  /* common-case tile sampler */
-    KG_KERNEL_QUEUE = 4    /* general base case for the tiles the sampler queued */
+    KG_KERNEL_COUNT = 0,   /* per-chunk counts (kg_rgg2d: the quadrant recursion) */
+    KG_KERNEL_SCAN = 1,    /* offsets (the scan of the wave sums and the fix-up; kg_rgg2d: both scans) */
+    KG_KERNEL_PLAN = 2,    /* tile plan (kg_gnp_skip: count pass; kg_rgg2d: edge count pass) */
+    KG_KERNEL_SAMPLE = 3,  /* common-case tile sampler (kg_gnp_skip, kg_rgg2d: write pass) */
+    KG_KERNEL_QUEUE = 4    /* general base case for the tiles the sampler queued (kg_rgg2d: points) */
 };
 kg_status kg_kernel_time_read(int kernel, double *ms_total, uint64_t *launches);
 

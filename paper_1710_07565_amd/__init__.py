@@ -7,6 +7,7 @@ from PyTorch, every step of the generator runs in the HIP library
 ``libkg.so`` (C ABI in include/kg.h).  Importing works without a GPU; calls
 need one and raise if the library has not been built.
 """
+import ctypes
 from dataclasses import dataclass
 
 from . import _lib
@@ -232,6 +233,62 @@ def gnp_skip(n, p, directed=True, seed=1, chunks=1, out=None, total=None, worksp
     if sized:
         return out
     return out, total
+
+
+def rgg2d_workspace_bytes(n, r):
+    b = ctypes.c_uint64(0)
+    _lib.check(_lib.lib().kg_rgg2d_workspace_bytes(int(n), float(r), ctypes.byref(b)), "kg_rgg2d_workspace_bytes")
+    return int(b.value)
+
+
+def rgg2d_expected_edges(n, r):
+    """Mean edge count of the two-dimensional RGG: C(n, 2) times the chance
+    that two uniform points of the unit square lie closer than r (for r <= 1:
+    pi r^2 - 8 r^3 / 3 + r^4 / 2)."""
+    import math
+    pairs = n * (n - 1) / 2.0
+    if r >= math.sqrt(2.0):
+        return pairs
+    if r <= 1.0:
+        return pairs * (math.pi * r * r - 8.0 * r ** 3 / 3.0 + r ** 4 / 2.0)
+    return pairs
+
+
+def rgg2d(n, r, seed=1, points=None, out=None, total=None, workspace=None, stream=None, device="cuda"):
+    """Two-dimensional random geometric graph (kg_rgg2d).  Returns
+    (points (n, 2) float64, edges (E, 2) uint32).  With `out` given, writes
+    into it and returns (points, out, total) without synchronising; if the
+    total exceeds out.shape[0] nothing is written to `out`."""
+    torch = _torch()
+    dev = out.device if out is not None else (points.device if points is not None else torch.device(device))
+    if points is None:
+        points = torch.empty((int(n), 2), dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(max(rgg2d_workspace_bytes(n, r), 1), dtype=torch.uint8, device=dev)
+    if total is None:
+        total = torch.zeros(1, dtype=torch.uint64, device=dev)
+
+    def call(edges):
+        st = _lib.lib().kg_rgg2d(int(n), float(r), int(seed) & (2**64 - 1),
+                                 points.data_ptr() if points.numel() else None,
+                                 edges.data_ptr() if edges.numel() else None, edges.shape[0], total.data_ptr(),
+                                 workspace.data_ptr(), workspace.numel(), _stream(stream))
+        _lib.check(st, "kg_rgg2d")
+
+    if out is not None:
+        call(out)
+        return points, out, total
+    import math
+    mu = rgg2d_expected_edges(int(n), float(r))
+    cap = int(min(n * (n - 1) // 2, mu * 1.05 + 8.0 * math.sqrt(mu + 1.0) * max(1.0, math.sqrt(n * r * r * 10.0))
+                  + 1024))
+    edges = torch.empty((max(cap, 0), 2), dtype=torch.uint32, device=dev)
+    call(edges)
+    E = int(total.view(torch.int64).cpu()[0])
+    if E > edges.shape[0]:
+        edges = torch.empty((E, 2), dtype=torch.uint32, device=dev)
+        call(edges)
+    return points, edges[:E]
 
 
 def batch_upload(instances, workspace, stream=None):

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkg.so")
 SOURCES = [os.path.join(HERE, "csrc", "kg_lib.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kg_device.hpp", "kg_kernels.hpp", "kg_tile.hpp", "kg_skip.hpp")] + \
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kg_device.hpp", "kg_kernels.hpp", "kg_tile.hpp", "kg_skip.hpp",
+                                                                   "kg_rgg.hpp")] + \
     [os.path.join(ROOT, "include", "kg.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KG_OFFLOAD_ARCH", "gfx950")

@@ -14,6 +14,7 @@
 #include "../../include/kg.h"
 #include "kg_tile.hpp"
 #include "kg_skip.hpp"
+#include "kg_rgg.hpp"
 
 namespace kg {
 __device__ double g_lnf_tab[kLnfTab + 1];
@@ -373,6 +374,62 @@ kg_instance make_inst(uint64_t n, uint32_t model, int directed, uint64_t m, doub
     return I;
 }
 
+// ---------------------------------------------------------------------------
+// Random geometric graphs: level rule and workspace layout.
+// ---------------------------------------------------------------------------
+uint32_t rgg_level(uint64_t n, double r)
+{
+    uint32_t L = 0;
+    while (L < kRggMaxLevel && ldexp(r, (int)L + 1) <= 1.0 && (1ull << (2 * (L + 1))) <= n) ++L;
+    return L;
+}
+
+struct RggLayout {
+    uint32_t L;
+    uint64_t C, nw, nbc, nbw;
+    uint64_t tree, coff, pcell, ecnt, wsum, woff, sums, status, total;
+};
+
+RggLayout rgg_layout(uint64_t n, double r)
+{
+    RggLayout Y;
+    Y.L = rgg_level(n, r);
+    Y.C = 1ull << (2 * Y.L);
+    Y.nw = (n + 63) / 64;
+    Y.nbc = (Y.C + kScanTile - 1) / kScanTile;
+    Y.nbw = Y.nw ? (Y.nw + kScanTile - 1) / kScanTile : 1;
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) { const uint64_t at = o; o += (bytes + 255) & ~255ull; return at; };
+    Y.tree = take(((1ull << (2 * (Y.L + 1))) - 1) / 3 * 8);
+    Y.coff = take((Y.C + 1) * 8);
+    Y.pcell = take(n * 4);
+    Y.ecnt = take(n * 4);
+    Y.wsum = take((Y.nw + 1) * 8);
+    Y.woff = take((Y.nw + 1) * 8);
+    Y.sums = take((std::max(Y.nbc, Y.nbw) + 1) * 8);
+    Y.status = take(4 * 8);
+    Y.total = o;
+    return Y;
+}
+
+kg_status rgg_check(uint64_t n, double r)
+{
+    if (!(r >= 0.0)) return KG_EINVAL;
+    if (n > 0xFFFFFFFFull) return KG_ERANGE;
+    const uint32_t L = rgg_level(n, r);
+    // expected points per cell times points: the per-point pass's work
+    if ((double)n * (double)n > ldexp(1.0, 36 + 2 * (int)L)) return KG_ERANGE;
+    return KG_OK;
+}
+
+void rgg_scan(const uint64_t *a, uint64_t len, uint64_t *sums, uint64_t *out, hipStream_t s)
+{
+    const uint64_t nb = len ? (len + kScanTile - 1) / kScanTile : 1;
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((uint32_t)nb), dim3(256), 0, s, a, len, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, sums, nb);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)nb), dim3(256), 0, s, a, len, (const uint64_t *)sums, out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -505,6 +562,88 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
         }
         if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
     }
+    release(ws, s);
+    return st;
+}
+
+kg_status kg_rgg2d_workspace_bytes(uint64_t n, double r, uint64_t *bytes)
+{
+    if (!bytes) return KG_EINVAL;
+    const kg_status st = rgg_check(n, r);
+    if (st) return st;
+    *bytes = rgg_layout(n, r).total;
+    return KG_OK;
+}
+
+kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32_t *d_edges,
+                   uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
+                   void *stream)
+{
+    kg_status st = rgg_check(n, r);
+    if (st) return st;
+    if (n > 0 && !d_points) return KG_EINVAL;
+    if (((uintptr_t)d_points & 15) != 0 || ((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    if (!d_edges) capacity_edges = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s) && !d_workspace) return KG_EINVAL;
+    int dev = 0;
+    st = ensure_init(&dev);
+    if (st) return st;
+    const RggLayout Y = rgg_layout(n, r);
+    Workspace ws;
+    st = acquire(ws, d_workspace, workspace_bytes, Y.total, s);
+    if (st) return st;
+    RggJob J;
+    memset(&J, 0, sizeof(J));
+    J.n = n;
+    J.seed = seed;
+    J.capacity = capacity_edges;
+    J.r2 = r * r;
+    J.h = ldexp(1.0, -(int)Y.L);
+    J.L = Y.L;
+    J.G = 1u << Y.L;
+    J.C = Y.C;
+    J.tree = (uint64_t *)(ws.base + Y.tree);
+    J.coff = (uint64_t *)(ws.base + Y.coff);
+    J.pcell = (uint32_t *)(ws.base + Y.pcell);
+    J.ecnt = (uint32_t *)(ws.base + Y.ecnt);
+    J.wsum = (uint64_t *)(ws.base + Y.wsum);
+    J.woff = (uint64_t *)(ws.base + Y.woff);
+    J.sums = (uint64_t *)(ws.base + Y.sums);
+    J.status = (uint64_t *)(ws.base + Y.status);
+    J.out_total = d_total;
+    J.pts = (double2 *)d_points;
+    J.edges = (uint2 *)d_edges;
+    {
+        KernelTimer tm(KG_KERNEL_COUNT, s);
+        hipLaunchKernelGGL(rgg_root_kernel, dim3(1), dim3(64), 0, s, J);
+        for (uint32_t l = 0; l < Y.L; ++l)
+            hipLaunchKernelGGL(rgg_split_kernel, dim3((uint32_t)(((1ull << (2 * l)) + 63) / 64)), dim3(64), 0, s,
+                               J, l);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SCAN, s);
+        rgg_scan(J.tree + ((Y.C - 1) / 3), Y.C, J.sums, J.coff, s);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_QUEUE, s);
+        hipLaunchKernelGGL(rgg_points_kernel, dim3((uint32_t)((Y.C + 63) / 64)), dim3(64), 0, s, J);
+    }
+    const uint64_t nwg = Y.nw ? Y.nw : 1;
+    {
+        KernelTimer tm(KG_KERNEL_PLAN, s);
+        hipLaunchKernelGGL(rgg_edges_kernel<false>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SCAN, s);
+        rgg_scan(J.wsum, Y.nw, J.sums, J.woff, s);
+        hipLaunchKernelGGL(rgg_total_kernel, dim3(1), dim3(64), 0, s, J, Y.nw);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SAMPLE, s);
+        hipLaunchKernelGGL(rgg_edges_kernel<true>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
+    }
+    if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
     release(ws, s);
     return st;
 }

@@ -1,0 +1,294 @@
+// kg_rgg.hpp -- two-dimensional random geometric graphs: n points uniform in
+// the unit square, an edge between every two points closer than r
+// (Sec. 2.1.2), generated as in Sec. 5: a grid of 4^L cells of side
+// 2^-L >= max(r, n^-1/2); the points per cell by a quadrant recursion of
+// binomial variates, each node drawing from a stream keyed by the node
+// (Sec. 5.1); the points of a cell from the cell's own stream; edges by
+// comparing each point with the points of its cell and the eight neighbours,
+// counted, prefix-summed and written in a second pass (Sec. 5.3).
+//
+// A node at level l (Morton index z) holding k points splits them with three
+// Bin(., 1/2) variates: the lower half (slot 0), its left quadrant (slot 1),
+// the upper half's left quadrant (slot 2); stream (seed; j, z, 3 l + slot,
+// TAG_RTREE).  Every node is computed once here, level by level; its value is
+// the one any root path to it would give, since it depends only on its own
+// count and stream.  Point j of cell z is ((cx + U) 2^-L, (cy + V) 2^-L), U
+// and V the two 64-bit uniforms of block j of (seed; j, z, 0, TAG_RPTS).
+// Vertex ids follow the cells in Morton order (x bit low, y bit high) and
+// the points within a cell; edges (u, v), u < v, with dx^2 + dy^2 < r^2 in
+// binary64 (each operation rounded), in ascending (u, v).
+#pragma once
+#include "kg_kernels.hpp"
+
+namespace kg {
+
+constexpr uint32_t TAG_RTREE = 8;
+constexpr uint32_t TAG_RPTS = 9;
+constexpr uint32_t kRggMaxLevel = 14;
+constexpr uint32_t kRggNone = 0xFFFFFFFFu;
+
+struct RggJob {
+    uint64_t n, seed, capacity;
+    double r2, h;              // r * r, cell side 2^-L
+    uint32_t L, G;             // level, cells per side
+    uint64_t C;                // cells
+    uint64_t *tree;            // node counts, level l at (4^l - 1) / 3, Morton order
+    uint64_t *coff;            // C + 1 first vertex id of every cell
+    uint32_t *pcell;           // n: cell of every vertex
+    uint32_t *ecnt;            // n: edges (u, v > u) of every vertex u
+    uint64_t *wsum;            // ceil(n / 64) + 1: edges per wave of vertices, then their offsets
+    uint64_t *woff;
+    uint64_t *sums;            // scan partials
+    uint64_t *status;          // [0] edges [1] overflow
+    uint64_t *out_total;
+    double2 *pts;
+    uint2 *edges;
+};
+
+__device__ __forceinline__ uint64_t rgg_level_base(uint32_t l) { return ((1ull << (2 * l)) - 1) / 3; }
+
+// Morton index <-> cell coordinates (L <= 14, so 28 bits)
+__device__ __forceinline__ uint32_t spread_bits(uint32_t x)
+{
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t gather_bits(uint32_t z)
+{
+    z &= 0x55555555u;
+    z = (z | (z >> 1)) & 0x33333333u;
+    z = (z | (z >> 2)) & 0x0F0F0F0Fu;
+    z = (z | (z >> 4)) & 0x00FF00FFu;
+    z = (z | (z >> 8)) & 0x0000FFFFu;
+    return z;
+}
+
+__global__ __launch_bounds__(64) void rgg_root_kernel(RggJob J)
+{
+    if (threadIdx.x == 0) J.tree[0] = J.n;
+}
+
+// One level of the quadrant recursion: lane per node of level l.
+__global__ __launch_bounds__(64) void rgg_split_kernel(RggJob J, uint32_t l)
+{
+    const uint64_t z = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    if (z >= (1ull << (2 * l))) return;
+    const uint64_t k = J.tree[rgg_level_base(l) + z];
+    const uint64_t lower = binom(make_stream(J.seed, (uint32_t)z, 3 * l + 0, TAG_RTREE), k, 0.5);
+    const uint64_t ll = binom(make_stream(J.seed, (uint32_t)z, 3 * l + 1, TAG_RTREE), lower, 0.5);
+    const uint64_t ul = binom(make_stream(J.seed, (uint32_t)z, 3 * l + 2, TAG_RTREE), k - lower, 0.5);
+    uint64_t *ch = J.tree + rgg_level_base(l + 1) + 4 * z;
+    ch[0] = ll;
+    ch[1] = lower - ll;
+    ch[2] = ul;
+    ch[3] = k - lower - ul;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of a u64 array of any length in three launches: tiles of
+// 4096 (256 threads x 16 consecutive items) reduced, the tile sums scanned by
+// one workgroup, the tiles scanned again with their prefix.  out[len] = total.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kScanItems = 16;
+constexpr uint64_t kScanTile = 256 * kScanItems;
+
+__device__ __forceinline__ uint64_t block256_excl_scan(uint64_t v, uint64_t &total)
+{
+    __shared__ uint64_t s_w[4];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t incl = wave_incl_scan64(v);
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+        const uint64_t x = s_w[i];
+        if (i < w) before += x;
+        tot += x;
+    }
+    total = tot;
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint64_t *a, uint64_t len, uint64_t *sums)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanItems; ++i)
+        if (base + i < len) s += a[base + i];
+    uint64_t total;
+    (void)block256_excl_scan(s, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// in place over sums[0, nb); sums[nb] = total
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t *sums, uint64_t nb)
+{
+    __shared__ uint64_t s_w[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < nb; base += 1024) {
+        const uint64_t i = base + t;
+        const uint64_t v = i < nb ? sums[i] : 0;
+        const uint64_t incl = wave_incl_scan64(v);
+        if (lane == 63) s_w[wv] = incl;
+        __syncthreads();
+        uint64_t before = carry, total = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            const uint64_t x = s_w[w];
+            if (w < wv) before += x;
+            total += x;
+        }
+        if (i < nb) sums[i] = before + incl - v;
+        carry += total;
+        __syncthreads();
+    }
+    if (t == 0) sums[nb] = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(const uint64_t *a, uint64_t len, const uint64_t *sums,
+                                                         uint64_t *out)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanItems; ++i) {
+        v[i] = base + i < len ? a[base + i] : 0;
+        s += v[i];
+    }
+    uint64_t total;
+    uint64_t run = block256_excl_scan(s, total) + sums[blockIdx.x];
+#pragma unroll
+    for (uint32_t i = 0; i < kScanItems; ++i) {
+        if (base + i < len) out[base + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = sums[gridDim.x];
+}
+
+// ---------------------------------------------------------------------------
+// Points: lane per cell.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void rgg_points_kernel(RggJob J)
+{
+    const uint64_t z = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    if (z >= J.C) return;
+    const uint64_t *cells = J.tree + rgg_level_base(J.L);
+    const uint64_t k = cells[z], o = J.coff[z];
+    const double cx = (double)gather_bits((uint32_t)z), cy = (double)gather_bits((uint32_t)z >> 1);
+    const Stream st = make_stream(J.seed, (uint32_t)z, 0, TAG_RPTS);
+    for (uint64_t j = 0; j < k; ++j) {
+        const U4 w = st.block((uint32_t)j);
+        const double U = unit_of(((uint64_t)w.y << 32) | w.x);
+        const double V = unit_of(((uint64_t)w.w << 32) | w.z);
+        J.pts[o + j] = make_double2((cx + U) * J.h, (cy + V) * J.h);
+        J.pcell[o + j] = (uint32_t)z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Edges: lane per vertex u.  The neighbour cells with Morton index >= u's
+// cell, in ascending index, hold the ids above u's cell in ascending order;
+// within u's own cell the candidates start at u + 1.  WRITE = false counts
+// (per vertex, and per wave of 64 vertices), WRITE = true stores at the
+// wave's offset plus the in-wave prefix.  Candidates are loaded four at a
+// time (independent loads in flight); the write pass gathers a wave's edges
+// (contiguous in the output) in LDS and stores them with consecutive lanes
+// on consecutive edges, unless they exceed the buffer.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRggStage = 1024;   // edges per wave gathered in LDS (8 KB)
+
+template <bool WRITE>
+__global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
+{
+    __shared__ uint2 s_e[WRITE ? kRggStage : 1];
+    const uint64_t u = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    uint64_t o = 0, wtotal = 0, lo = 0;
+    if (WRITE) {
+        if (J.status[1]) return;
+        const uint64_t k = u < J.n ? J.ecnt[u] : 0;
+        const uint64_t incl = wave_incl_scan64(k);
+        lo = incl - k;
+        wtotal = __shfl(incl, 63, 64);
+        o = J.woff[blockIdx.x];
+    }
+    const bool staged = wtotal <= kRggStage;
+    uint32_t cnt = 0;
+    if (u < J.n) {
+        const uint32_t z = J.pcell[u];
+        const int cx = (int)gather_bits(z), cy = (int)gather_bits(z >> 1);
+        uint32_t nb[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int x = cx + i % 3 - 1, y = cy + i / 3 - 1;
+            const bool in = x >= 0 && y >= 0 && x < (int)J.G && y < (int)J.G;
+            const uint32_t zz = in ? (spread_bits((uint32_t)x) | (spread_bits((uint32_t)y) << 1)) : kRggNone;
+            nb[i] = zz >= z ? zz : kRggNone;
+        }
+        // odd-even transposition sort of the nine indices
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+#pragma unroll
+            for (int i = r & 1; i + 1 < 9; i += 2) {
+                const uint32_t a = min(nb[i], nb[i + 1]), b = max(nb[i], nb[i + 1]);
+                nb[i] = a;
+                nb[i + 1] = b;
+            }
+        }
+        const double2 p = J.pts[u];
+        const double r2 = J.r2;
+        auto test = [&](const double2 q, uint64_t b) {
+            const double dx = p.x - q.x, dy = p.y - q.y;
+            if (dx * dx + dy * dy < r2) {
+                if (WRITE) {
+                    const uint2 e = make_uint2((uint32_t)u, (uint32_t)b);
+                    if (staged) s_e[lo + cnt] = e;
+                    else J.edges[o + lo + cnt] = e;
+                }
+                ++cnt;
+            }
+        };
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const uint32_t zz = nb[i];
+            if (zz == kRggNone) continue;
+            const uint64_t b1 = J.coff[zz + 1];
+            uint64_t b = zz == z ? u + 1 : J.coff[zz];
+            for (; b + 4 <= b1; b += 4) {
+                const double2 q0 = J.pts[b], q1 = J.pts[b + 1], q2 = J.pts[b + 2], q3 = J.pts[b + 3];
+                test(q0, b);
+                test(q1, b + 1);
+                test(q2, b + 2);
+                test(q3, b + 3);
+            }
+            for (; b < b1; ++b) test(J.pts[b], b);
+        }
+    }
+    if (!WRITE) {
+        if (u < J.n) J.ecnt[u] = cnt;
+        const uint64_t incl = wave_incl_scan64((uint64_t)cnt);
+        if (threadIdx.x == 63) J.wsum[blockIdx.x] = incl;
+    } else if (staged) {
+        __syncthreads();
+        for (uint64_t i = threadIdx.x; i < wtotal; i += 64) J.edges[o + i] = s_e[i];
+    }
+}
+
+// The total, the overflow flag and the caller's copy of the total.
+__global__ __launch_bounds__(64) void rgg_total_kernel(RggJob J, uint64_t nw)
+{
+    if (threadIdx.x != 0) return;
+    const uint64_t E = J.woff[nw];
+    J.status[0] = E;
+    J.status[1] = E > J.capacity ? 1 : 0;
+    if (J.out_total) *J.out_total = E;
+}
+
+}  // namespace kg
