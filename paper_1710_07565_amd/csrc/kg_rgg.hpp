@@ -35,7 +35,8 @@ struct RggJob {
     uint64_t *tree;            // node counts, level l at (4^l - 1) / 3, Morton order
     uint64_t *coff;            // C + 1 first vertex id of every cell
     uint32_t *pcell;           // n: cell of every vertex
-    uint32_t *ecnt;            // n: edges (u, v > u) of every vertex u
+    uint32_t *ecnt;            // n: edges (u, v > u) of every vertex u; top bit: more candidates than recorded
+    uint64_t *bits;            // kRggBitWords x n (word-major): the count pass's test results per candidate
     uint64_t *wsum;            // ceil(n / 64) + 1: edges per wave of vertices, then their offsets
     uint64_t *woff;
     uint64_t *sums;            // scan partials
@@ -196,14 +197,22 @@ __global__ __launch_bounds__(64) void rgg_points_kernel(RggJob J)
 // ---------------------------------------------------------------------------
 // Edges: lane per vertex u.  The neighbour cells with Morton index >= u's
 // cell, in ascending index, hold the ids above u's cell in ascending order;
-// within u's own cell the candidates start at u + 1.  WRITE = false counts
-// (per vertex, and per wave of 64 vertices), WRITE = true stores at the
-// wave's offset plus the in-wave prefix.  Candidates are loaded four at a
-// time (independent loads in flight); the write pass gathers a wave's edges
-// (contiguous in the output) in LDS and stores them with consecutive lanes
-// on consecutive edges, unless they exceed the buffer.
+// within u's own cell the candidates start at u + 1.
+//
+// Count pass (WRITE = false): every candidate is tested (four loads in
+// flight); the results of the first 64 kRggBitWords candidates are kept as
+// a bit mask per vertex (word w of vertex u at bits[w n + u], so a wave's
+// stores are contiguous), the edge count per vertex and per wave of 64
+// vertices are stored; a vertex with more candidates is flagged.
+// Write pass (WRITE = true): at the wave's offset plus the in-wave prefix,
+// the edges are read off the mask (candidate order again, set bits only);
+// flagged vertices test their candidates again.  A wave's edges are
+// contiguous in the output: they are gathered in LDS and stored with
+// consecutive lanes on consecutive edges, unless they exceed the buffer.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRggStage = 1024;   // edges per wave gathered in LDS (8 KB)
+constexpr uint32_t kRggBitWords = 4;   // candidates recorded per vertex: 256
+constexpr uint32_t kRggMore = 0x80000000u;
 
 template <bool WRITE>
 __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
@@ -211,9 +220,12 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
     __shared__ uint2 s_e[WRITE ? kRggStage : 1];
     const uint64_t u = (uint64_t)blockIdx.x * 64 + threadIdx.x;
     uint64_t o = 0, wtotal = 0, lo = 0;
+    bool more = false;
     if (WRITE) {
         if (J.status[1]) return;
-        const uint64_t k = u < J.n ? J.ecnt[u] : 0;
+        const uint32_t e = u < J.n ? J.ecnt[u] : 0;
+        more = (e & kRggMore) != 0;
+        const uint64_t k = e & ~kRggMore;
         const uint64_t incl = wave_incl_scan64(k);
         lo = incl - k;
         wtotal = __shfl(incl, 63, 64);
@@ -221,6 +233,7 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
     }
     const bool staged = wtotal <= kRggStage;
     uint32_t cnt = 0;
+    uint64_t c = 0;       // candidates seen
     if (u < J.n) {
         const uint32_t z = J.pcell[u];
         const int cx = (int)gather_bits(z), cy = (int)gather_bits(z >> 1);
@@ -242,37 +255,79 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
                 nb[i + 1] = b;
             }
         }
-        const double2 p = J.pts[u];
-        const double r2 = J.r2;
-        auto test = [&](const double2 q, uint64_t b) {
-            const double dx = p.x - q.x, dy = p.y - q.y;
-            if (dx * dx + dy * dy < r2) {
-                if (WRITE) {
-                    const uint2 e = make_uint2((uint32_t)u, (uint32_t)b);
-                    if (staged) s_e[lo + cnt] = e;
-                    else J.edges[o + lo + cnt] = e;
-                }
-                ++cnt;
-            }
+        auto emit = [&](uint64_t b) {
+            const uint2 e = make_uint2((uint32_t)u, (uint32_t)b);
+            if (staged) s_e[lo + cnt] = e;
+            else J.edges[o + lo + cnt] = e;
+            ++cnt;
         };
+        if (!WRITE || more) {
+            const double2 p = J.pts[u];
+            const double r2 = J.r2;
+            uint64_t cur = 0;
+            auto test = [&](const double2 q, uint64_t b) {
+                const double dx = p.x - q.x, dy = p.y - q.y;
+                const bool hit = dx * dx + dy * dy < r2;
+                if (WRITE) {
+                    if (hit) emit(b);
+                } else {
+                    cnt += hit ? 1u : 0u;
+                    cur |= (uint64_t)hit << (c & 63);
+                    ++c;
+                    if ((c & 63) == 0) {
+                        if (c <= 64ull * kRggBitWords) J.bits[((c >> 6) - 1) * J.n + u] = cur;
+                        cur = 0;
+                    }
+                }
+            };
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const uint32_t zz = nb[i];
-            if (zz == kRggNone) continue;
-            const uint64_t b1 = J.coff[zz + 1];
-            uint64_t b = zz == z ? u + 1 : J.coff[zz];
-            for (; b + 4 <= b1; b += 4) {
-                const double2 q0 = J.pts[b], q1 = J.pts[b + 1], q2 = J.pts[b + 2], q3 = J.pts[b + 3];
-                test(q0, b);
-                test(q1, b + 1);
-                test(q2, b + 2);
-                test(q3, b + 3);
+            for (int i = 0; i < 9; ++i) {
+                const uint32_t zz = nb[i];
+                if (zz == kRggNone) continue;
+                const uint64_t b1 = J.coff[zz + 1];
+                uint64_t b = zz == z ? u + 1 : J.coff[zz];
+                for (; b + 4 <= b1; b += 4) {
+                    const double2 q0 = J.pts[b], q1 = J.pts[b + 1], q2 = J.pts[b + 2], q3 = J.pts[b + 3];
+                    test(q0, b);
+                    test(q1, b + 1);
+                    test(q2, b + 2);
+                    test(q3, b + 3);
+                }
+                for (; b < b1; ++b) test(J.pts[b], b);
             }
-            for (; b < b1; ++b) test(J.pts[b], b);
+            if (!WRITE && (c & 63) != 0 && c < 64ull * kRggBitWords) J.bits[(c >> 6) * J.n + u] = cur;
+        } else {
+            // the recorded results: walk the candidates in the same order,
+            // a word at a time, and emit the set bits
+            uint32_t wcur = kRggNone;
+            uint64_t word = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint32_t zz = nb[i];
+                if (zz == kRggNone) continue;
+                const uint64_t b1 = J.coff[zz + 1];
+                uint64_t b = zz == z ? u + 1 : J.coff[zz];
+                while (b < b1) {
+                    const uint32_t w = (uint32_t)(c >> 6), off = (uint32_t)(c & 63);
+                    if (w != wcur) {
+                        word = J.bits[(uint64_t)w * J.n + u];
+                        wcur = w;
+                    }
+                    const uint64_t take = min((uint64_t)(64 - off), b1 - b);
+                    uint64_t m = word >> off;
+                    if (take < 64) m &= (1ull << take) - 1;
+                    while (m) {
+                        emit(b + (uint64_t)__builtin_ctzll(m));
+                        m &= m - 1;
+                    }
+                    b += take;
+                    c += take;
+                }
+            }
         }
     }
     if (!WRITE) {
-        if (u < J.n) J.ecnt[u] = cnt;
+        if (u < J.n) J.ecnt[u] = cnt | (c > 64ull * kRggBitWords ? kRggMore : 0u);
         const uint64_t incl = wave_incl_scan64((uint64_t)cnt);
         if (threadIdx.x == 63) J.wsum[blockIdx.x] = incl;
     } else if (staged) {
