@@ -261,24 +261,51 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
             else J.edges[o + lo + cnt] = e;
             ++cnt;
         };
-        if (!WRITE || more) {
+        if (!WRITE) {
             const double2 p = J.pts[u];
             const double r2 = J.r2;
             uint64_t cur = 0;
+            auto hit = [&](const double2 q) -> uint32_t {
+                const double dx = p.x - q.x, dy = p.y - q.y;
+                return dx * dx + dy * dy < r2 ? 1u : 0u;
+            };
+            // append nbits (1..4) result bits v to the mask: a full word is
+            // stored (if recorded), a word boundary inside v carries over
+            auto put = [&](uint32_t v, uint32_t nbits) {
+                const uint32_t off = (uint32_t)(c & 63);
+                const uint64_t w = c >> 6;
+                cur |= (uint64_t)v << off;
+                c += nbits;
+                if (off + nbits >= 64) {
+                    if (w < kRggBitWords) J.bits[w * J.n + u] = cur;
+                    cur = off + nbits > 64 ? (uint64_t)(v >> (64 - off)) : 0;
+                }
+            };
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint32_t zz = nb[i];
+                if (zz == kRggNone) continue;
+                const uint64_t b1 = J.coff[zz + 1];
+                uint64_t b = zz == z ? u + 1 : J.coff[zz];
+                for (; b + 4 <= b1; b += 4) {
+                    const double2 q0 = J.pts[b], q1 = J.pts[b + 1], q2 = J.pts[b + 2], q3 = J.pts[b + 3];
+                    const uint32_t v = hit(q0) | (hit(q1) << 1) | (hit(q2) << 2) | (hit(q3) << 3);
+                    cnt += (uint32_t)__builtin_popcount(v);
+                    put(v, 4);
+                }
+                for (; b < b1; ++b) {
+                    const uint32_t v = hit(J.pts[b]);
+                    cnt += v;
+                    put(v, 1);
+                }
+            }
+            if ((c & 63) != 0 && (c >> 6) < kRggBitWords) J.bits[(c >> 6) * J.n + u] = cur;
+        } else if (more) {
+            const double2 p = J.pts[u];
+            const double r2 = J.r2;
             auto test = [&](const double2 q, uint64_t b) {
                 const double dx = p.x - q.x, dy = p.y - q.y;
-                const bool hit = dx * dx + dy * dy < r2;
-                if (WRITE) {
-                    if (hit) emit(b);
-                } else {
-                    cnt += hit ? 1u : 0u;
-                    cur |= (uint64_t)hit << (c & 63);
-                    ++c;
-                    if ((c & 63) == 0) {
-                        if (c <= 64ull * kRggBitWords) J.bits[((c >> 6) - 1) * J.n + u] = cur;
-                        cur = 0;
-                    }
-                }
+                if (dx * dx + dy * dy < r2) emit(b);
             };
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -295,7 +322,6 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
                 }
                 for (; b < b1; ++b) test(J.pts[b], b);
             }
-            if (!WRITE && (c & 63) != 0 && c < 64ull * kRggBitWords) J.bits[(c >> 6) * J.n + u] = cur;
         } else {
             // the recorded results: walk the candidates in the same order,
             // a word at a time, and emit the set bits
