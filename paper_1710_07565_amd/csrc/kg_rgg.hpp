@@ -210,7 +210,7 @@ __global__ __launch_bounds__(64) void rgg_points_kernel(RggJob J)
 // contiguous in the output: they are gathered in LDS and stored with
 // consecutive lanes on consecutive edges, unless they exceed the buffer.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kRggStage = 1024;   // edges per wave gathered in LDS (8 KB)
+constexpr uint32_t kRggStage = 640;    // edges per wave gathered in LDS (5 KB)
 constexpr uint32_t kRggBitWords = 4;   // candidates recorded per vertex: 256
 constexpr uint32_t kRggMore = 0x80000000u;
 
