@@ -175,22 +175,35 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const uint64_t *a, uint
 }
 
 // ---------------------------------------------------------------------------
-// Points: lane per cell.
+// Points: a wave per 64 consecutive cells, whose points are consecutive
+// vertices; lane per point (stores of consecutive lanes are contiguous).  A
+// point's cell is the last of the wave's cells whose first vertex is <= it
+// (a binary search over the 64 offsets held one per lane).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void rgg_points_kernel(RggJob J)
 {
-    const uint64_t z = (uint64_t)blockIdx.x * 64 + threadIdx.x;
-    if (z >= J.C) return;
-    const uint64_t *cells = J.tree + rgg_level_base(J.L);
-    const uint64_t k = cells[z], o = J.coff[z];
-    const double cx = (double)gather_bits((uint32_t)z), cy = (double)gather_bits((uint32_t)z >> 1);
-    const Stream st = make_stream(J.seed, (uint32_t)z, 0, TAG_RPTS);
-    for (uint64_t j = 0; j < k; ++j) {
-        const U4 w = st.block((uint32_t)j);
-        const double U = unit_of(((uint64_t)w.y << 32) | w.x);
-        const double V = unit_of(((uint64_t)w.w << 32) | w.z);
-        J.pts[o + j] = make_double2((cx + U) * J.h, (cy + V) * J.h);
-        J.pcell[o + j] = (uint32_t)z;
+    const uint64_t z0 = (uint64_t)blockIdx.x * 64;
+    const uint32_t lane = threadIdx.x;
+    const uint64_t first = J.coff[min(z0 + lane, J.C)];
+    const uint64_t start = J.coff[z0], end = J.coff[min(z0 + 64, J.C)];
+    for (uint64_t base = start; base < end; base += 64) {
+        const uint64_t p = base + lane;
+        uint32_t l = 0;
+#pragma unroll
+        for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint64_t v = __shfl(first, (int)(l + step), 64);
+            if (v <= p) l += step;
+        }
+        const uint64_t j = p - __shfl(first, (int)l, 64);
+        if (p < end) {
+            const uint32_t z = (uint32_t)(z0 + l);
+            const double cx = (double)gather_bits(z), cy = (double)gather_bits(z >> 1);
+            const U4 w = make_stream(J.seed, z, 0, TAG_RPTS).block((uint32_t)j);
+            const double U = unit_of(((uint64_t)w.y << 32) | w.x);
+            const double V = unit_of(((uint64_t)w.w << 32) | w.z);
+            J.pts[p] = make_double2((cx + U) * J.h, (cy + V) * J.h);
+            J.pcell[p] = z;
+        }
     }
 }
 
