@@ -128,3 +128,31 @@ def test_skip_variant_argument_checks(L):
     assert L.kg_gnp_skip(100, 0.1, 1, 1, 0, None, 0, None, None, 0, None) == _lib.KG_EINVAL
     assert L.kg_gnp_skip(100, 0.1, 1, 1, 4, 4, 10, None, None, 0, None) == _lib.KG_EINVAL   # misaligned
     assert L.kg_gnp_skip(2**33, 0.1, 1, 1, 4, None, 0, None, None, 0, None) == _lib.KG_ERANGE
+
+
+def test_rgg_argument_checks_and_workspace(L):
+    """kg_rgg2d and its workspace query validate on the host: negative or
+    NaN radius, n >= 2^32, too many points per cell, missing or misaligned
+    point buffer; the workspace grows with the level rule's cell count."""
+    import ctypes
+    from paper_1710_07565_amd import _lib
+    b = ctypes.c_uint64(0)
+    assert L.kg_rgg2d_workspace_bytes(100, -0.1, ctypes.byref(b)) == _lib.KG_EINVAL
+    assert L.kg_rgg2d_workspace_bytes(100, float("nan"), ctypes.byref(b)) == _lib.KG_EINVAL
+    assert L.kg_rgg2d_workspace_bytes(2**32, 0.001, ctypes.byref(b)) == _lib.KG_ERANGE
+    assert L.kg_rgg2d_workspace_bytes(10**6, 0.6, ctypes.byref(b)) == _lib.KG_ERANGE   # one cell
+    assert L.kg_rgg2d_workspace_bytes(100, 0.1, None) == _lib.KG_EINVAL
+    sizes = []
+    for n, r in [(0, 0.5), (1000, 0.5), (1000, 0.1), (1000, 0.01), (10**6, 0.001)]:
+        assert L.kg_rgg2d_workspace_bytes(n, r, ctypes.byref(b)) == _lib.KG_OK
+        sizes.append(b.value)
+    assert sizes[0] > 0 and sizes[1] < sizes[2] < sizes[3] < sizes[4]
+    # n = 2^26 at the benchmark radius: 4^11 cells, about 40 B per vertex plus the tree
+    import math
+    n = 2**26
+    assert L.kg_rgg2d_workspace_bytes(n, 0.55 * math.sqrt(math.log(n) / n), ctypes.byref(b)) == _lib.KG_OK
+    assert 40 * n < b.value < 40 * n + 64 * 4**11
+    assert L.kg_rgg2d(100, -1.0, 1, None, None, 0, None, None, 0, None) == _lib.KG_EINVAL
+    assert L.kg_rgg2d(100, 0.1, 1, None, None, 0, None, None, 0, None) == _lib.KG_EINVAL      # no points
+    assert L.kg_rgg2d(100, 0.1, 1, 8, None, 0, None, None, 0, None) == _lib.KG_EINVAL         # misaligned
+    assert L.kg_rgg2d(2**32, 0.1, 1, None, None, 0, None, None, 0, None) == _lib.KG_ERANGE

@@ -112,3 +112,34 @@ def test_capture_refuses_host_work():
     torch.cuda.synchronize()
     assert torch.equal(arena.view(torch.int32), ref_arena.view(torch.int32))
     assert torch.equal(offs.view(torch.int64), ref_offs.view(torch.int64))
+
+
+def test_captured_rgg2d_replays_equal_eager():
+    """kg_rgg2d with a caller workspace only enqueues kernels: recorded into
+    a graph and replayed, it rewrites the eager call's points and edges."""
+    import torch
+    kg = require_gpu()
+    n, r, seed = 50000, 0.006, 4
+    P0, E0 = kg.rgg2d(n, r, seed)
+    torch.cuda.synchronize()
+    wantP, wantE = P0.cpu().view(torch.int64).numpy(), to_np_u32(E0)
+    pts = torch.empty_like(P0)
+    out = torch.empty((E0.shape[0] + 16, 2), dtype=torch.uint32, device="cuda")
+    tot = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    ws = torch.empty(kg.rgg2d_workspace_bytes(n, r), dtype=torch.uint8, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=side):
+        kg.rgg2d(n, r, seed, points=pts, out=out, total=tot, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        pts.zero_()
+        out.zero_()
+        tot.zero_()
+        g.replay()
+        kg.rgg2d(3000, 0.03, rep)      # eager work between replays, on its own buffers
+        torch.cuda.synchronize()
+        assert int(tot.view(torch.int64).cpu()[0]) == len(wantE), rep
+        assert np.array_equal(pts.cpu().view(torch.int64).numpy(), wantP), rep
+        assert np.array_equal(to_np_u32(out)[:len(wantE)], wantE), rep
