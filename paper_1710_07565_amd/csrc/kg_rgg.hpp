@@ -226,6 +226,7 @@ __global__ __launch_bounds__(64) void rgg_points_kernel(RggJob J)
 constexpr uint32_t kRggStage = 640;    // edges per wave gathered in LDS (5 KB)
 constexpr uint32_t kRggBitWords = 4;   // candidates recorded per vertex: 256
 constexpr uint32_t kRggMore = 0x80000000u;
+constexpr uint32_t kRggWinPts = 320;   // window points a count-pass wave copies to LDS (5 KB)
 
 template <bool WRITE>
 __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
@@ -245,6 +246,69 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
         o = J.woff[blockIdx.x];
     }
     const bool staged = wtotal <= kRggStage;
+    // count pass: the points of every cell some lane of the wave needs
+    // (the windows of the wave's cells, Morton index >= the cell), copied
+    // to LDS once, if they fit: the candidate tests then read LDS
+    __shared__ double2 s_p[WRITE ? 1 : kRggWinPts];
+    __shared__ uint32_t s_cz[WRITE ? 1 : 64], s_co[WRITE ? 1 : 65];
+    __shared__ uint64_t s_cs[WRITE ? 1 : 64];
+    uint32_t U = 0;
+    bool win = false;
+    if (!WRITE && (uint64_t)blockIdx.x * 64 < J.n) {
+        const uint32_t l = threadIdx.x;
+        const uint64_t u0 = (uint64_t)blockIdx.x * 64;
+        const uint64_t ul = u0 + 63 < J.n ? u0 + 63 : J.n - 1;
+        const uint32_t zlo = J.pcell[u0], zhi = J.pcell[ul];
+        if (9ull * (zhi - zlo + 1) <= 64) {
+            uint32_t v = kRggNone;
+            if (l < 9 * (zhi - zlo + 1)) {
+                const uint32_t zc = zlo + l / 9;
+                const int i = (int)(l % 9);
+                const int x = (int)gather_bits(zc) + i % 3 - 1, y = (int)gather_bits(zc >> 1) + i / 3 - 1;
+                if (x >= 0 && y >= 0 && x < (int)J.G && y < (int)J.G) {
+                    const uint32_t zz = spread_bits((uint32_t)x) | (spread_bits((uint32_t)y) << 1);
+                    if (zz >= zc) v = zz;
+                }
+            }
+            // bitonic sort of the 64 lane values, ascending
+#pragma unroll
+            for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    const uint32_t w = (uint32_t)__shfl_xor((int)v, (int)j, 64);
+                    v = (((l & j) == 0) == ((l & k) == 0)) ? min(v, w) : max(v, w);
+                }
+            }
+            const uint32_t prev = (uint32_t)__shfl_up((int)v, 1, 64);
+            const bool uniq = v != kRggNone && (l == 0 || v != prev);
+            const uint64_t m = __ballot(uniq);
+            U = (uint32_t)__popcll(m);
+            const uint32_t idx = (uint32_t)__popcll(m & lanemask_lt(l));
+            uint64_t st = 0, ct = 0;
+            if (uniq) {
+                st = J.coff[v];
+                ct = J.coff[v + 1] - st;
+            }
+            const uint64_t incl = wave_incl_scan64(ct);
+            const uint64_t total = __shfl(incl, 63, 64);
+            if (total <= kRggWinPts) {
+                if (uniq) {
+                    s_cz[idx] = v;
+                    s_cs[idx] = st;
+                    s_co[idx] = (uint32_t)(incl - ct);
+                }
+                if (l == 0) s_co[U] = (uint32_t)total;
+                __syncthreads();
+                for (uint32_t i = 0; i < U; ++i) {
+                    const uint32_t ob = s_co[i], len = s_co[i + 1] - ob;
+                    const uint64_t sb = s_cs[i];
+                    for (uint32_t t = l; t < len; t += 64) s_p[ob + t] = J.pts[sb + t];
+                }
+                __syncthreads();
+                win = true;
+            }
+        }
+    }
     uint32_t cnt = 0;
     uint64_t c = 0;       // candidates seen
     if (u < J.n) {
@@ -294,22 +358,52 @@ __global__ __launch_bounds__(64) void rgg_edges_kernel(RggJob J)
                     cur = off + nbits > 64 ? (uint64_t)(v >> (64 - off)) : 0;
                 }
             };
+            if (win) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const uint32_t zz = nb[i];
-                if (zz == kRggNone) continue;
-                const uint64_t b1 = J.coff[zz + 1];
-                uint64_t b = zz == z ? u + 1 : J.coff[zz];
-                for (; b + 4 <= b1; b += 4) {
-                    const double2 q0 = J.pts[b], q1 = J.pts[b + 1], q2 = J.pts[b + 2], q3 = J.pts[b + 3];
-                    const uint32_t v = hit(q0) | (hit(q1) << 1) | (hit(q2) << 2) | (hit(q3) << 3);
-                    cnt += (uint32_t)__builtin_popcount(v);
-                    put(v, 4);
+                for (int i = 0; i < 9; ++i) {
+                    const uint32_t zz = nb[i];
+                    if (zz == kRggNone) continue;
+                    uint32_t a = 0, e = U;
+                    while (e - a > 1) {
+                        const uint32_t mid = (a + e) >> 1;
+                        if (s_cz[mid] <= zz) a = mid;
+                        else e = mid;
+                    }
+                    const uint64_t sb = s_cs[a];
+                    const uint32_t ob = s_co[a];
+                    const uint32_t t1 = s_co[a + 1] - ob;
+                    uint32_t t = zz == z ? (uint32_t)(u + 1 - sb) : 0;
+                    for (; t + 4 <= t1; t += 4) {
+                        const double2 q0 = s_p[ob + t], q1 = s_p[ob + t + 1], q2 = s_p[ob + t + 2],
+                                      q3 = s_p[ob + t + 3];
+                        const uint32_t v = hit(q0) | (hit(q1) << 1) | (hit(q2) << 2) | (hit(q3) << 3);
+                        cnt += (uint32_t)__builtin_popcount(v);
+                        put(v, 4);
+                    }
+                    for (; t < t1; ++t) {
+                        const uint32_t v = hit(s_p[ob + t]);
+                        cnt += v;
+                        put(v, 1);
+                    }
                 }
-                for (; b < b1; ++b) {
-                    const uint32_t v = hit(J.pts[b]);
-                    cnt += v;
-                    put(v, 1);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const uint32_t zz = nb[i];
+                    if (zz == kRggNone) continue;
+                    const uint64_t b1 = J.coff[zz + 1];
+                    uint64_t b = zz == z ? u + 1 : J.coff[zz];
+                    for (; b + 4 <= b1; b += 4) {
+                        const double2 q0 = J.pts[b], q1 = J.pts[b + 1], q2 = J.pts[b + 2], q3 = J.pts[b + 3];
+                        const uint32_t v = hit(q0) | (hit(q1) << 1) | (hit(q2) << 2) | (hit(q3) << 3);
+                        cnt += (uint32_t)__builtin_popcount(v);
+                        put(v, 4);
+                    }
+                    for (; b < b1; ++b) {
+                        const uint32_t v = hit(J.pts[b]);
+                        cnt += v;
+                        put(v, 1);
+                    }
                 }
             }
             if ((c & 63) != 0 && (c >> 6) < kRggBitWords) J.bits[(c >> 6) * J.n + u] = cur;
