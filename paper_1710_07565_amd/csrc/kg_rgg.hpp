@@ -212,8 +212,11 @@ __global__ __launch_bounds__(64) void rgg_points_kernel(RggJob J)
 // cell, in ascending index, hold the ids above u's cell in ascending order;
 // within u's own cell the candidates start at u + 1.
 //
-// Count pass (WRITE = false): every candidate is tested (four loads in
-// flight); the results of the first 64 kRggBitWords candidates are kept as
+// Count pass (WRITE = false): every candidate is tested, four at a time.
+// The wave first gathers the cells its vertices need (the windows of its at
+// most seven cells, deduplicated by a sort across the lanes) and, if their
+// points fit, copies them to LDS once; the tests then read LDS instead of
+// global memory.  The results of the first 64 kRggBitWords candidates are kept as
 // a bit mask per vertex (word w of vertex u at bits[w n + u], so a wave's
 // stores are contiguous), the edge count per vertex and per wave of 64
 // vertices are stored; a vertex with more candidates is flagged.
