@@ -112,6 +112,18 @@ def write_traffic(workload, fetch_dir, write_dir, copy_gib, commands):
     log("traffic for %s: %.4g bytes per launch" % (workload, total))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(desc, seconds):
     """The oracle (plain C, OpenMP over chunks) on a bounded sample of the
     same workload: whole chunks in canonical order, blocks of 256, until
@@ -156,6 +168,7 @@ def cpu_baseline(desc, seconds):
         if t1 >= seconds / 5:
             break
     return {"value": edges / t, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "%d of %d chunks (%d edges, %.1f s), seed 1" % (done, C, edges, t),
             "one_thread": {"value": e1 / t1, "unit": "edges/s", "edges": e1, "seconds": t1}}
 
@@ -196,9 +209,7 @@ def run_plain(args, desc):
         else:
             edges_per_step.append(kg.gnp_count(n, p, directed, seeds[i % len(seeds)], P, workspace=ws))
     torch.cuda.synchronize()
-    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
-    for k in range(5):
-        kg.kernel_time_read(k)
+    # the timed steps: one kg_gnm / kg_gnp call each, nothing else enqueued
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -208,9 +219,22 @@ def run_plain(args, desc):
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
     ms = ev[0].elapsed_time(ev[-1])
     per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+    # the same steps again with every kernel launch bracketed by HIP events
+    # recorded on the launch stream (the per-kernel split and the sampler's
+    # launch time for the roofline)
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
+    for k in range(5):
+        kg.kernel_time_read(k)
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
+    ms_split = f0.elapsed_time(f1)
     kt = {nm: kg.kernel_time_read(k) for k, nm in ((0, "count"), (1, "scan"), (2, "plan"), (3, "sample"),
                                                    (4, "queue"))}
     if model == 1:
@@ -240,6 +264,7 @@ def run_plain(args, desc):
                      "kernel": ROOFLINE_KERNEL, "avg_launch_ms": samp_avg,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "kernel_split_pass_ms_per_step": ms_split / args.steps,
         "wall_s_timed": wall,
     }
     return res
@@ -464,7 +489,7 @@ def run_views(args):
             if _t.perf_counter() - t0 > args.cpu_seconds:
                 break
         dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": cnt / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        res["cpu_baseline"] = {"value": cnt / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": "%d of %d views (%d edges, %.1f s), one thread" % (done, P, cnt, dt)}
     else:
         res["cpu_baseline"] = None
@@ -539,7 +564,7 @@ def run_skip(args):
             cnt += len(kgref.skip_chunk_edges(I, c))
             c += 1
         dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": cnt / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        res["cpu_baseline"] = {"value": cnt / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": "%d of %d chunks (%d edges, %.1f s), one thread" % (c, P, cnt, dt)}
     else:
         res["cpu_baseline"] = None
@@ -618,12 +643,49 @@ def run_rgg(args):
         t0 = _t.perf_counter()
         _, Es = kgref.rgg2d(ns, rs, 1)
         dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": len(Es) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        res["cpu_baseline"] = {"value": len(Es) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": "n=2^22, r=0.55 sqrt(ln n/n), seed 1: %d edges in %.1f s, one thread"
                                % (len(Es), dt)}
     else:
         res["cpu_baseline"] = None
     return res
+
+
+def served_summary(args, duration, warmup_s, sat_rate, sat_seconds):
+    """The served workload for the default line: Poisson arrivals at
+    args.rate for `duration` s with the client's checks on (checksum of every
+    request on the device, the length of every G(n,m) list, a 1% sample
+    re-generated alone), then one saturation step at `sat_rate` for
+    `sat_seconds` s (checks off)."""
+    import torch
+    import paper_1710_07565_amd as kg
+    from paper_1710_07565_amd import serve, workloads
+    torch.cuda.set_device(0)
+    srv = serve.Server(budget_bytes=int(args.budget_gb * 1e9), streams=args.streams, max_batch=args.max_batch,
+                       verify=True, alone_every=100)
+    w = workloads.request_stream(rate_per_s=200.0, duration_s=0.5, base_seed=99, seed_fn=kg.instance_seed)
+    serve.run_stream(srv, w, warmup_s=0.0)
+    stream = workloads.request_stream(rate_per_s=args.rate, duration_s=duration, base_seed=1,
+                                      seed_fn=kg.instance_seed)
+    log("bench: serving %d requests over %.0f s at %.0f req/s (client checks on)" % (len(stream), duration,
+                                                                                     args.rate))
+    _, st = serve.run_stream(srv, stream, warmup_s=warmup_s)
+    srv.verify = False
+    srv.rejected = 0
+    sat = workloads.request_stream(rate_per_s=sat_rate, duration_s=sat_seconds, base_seed=2,
+                                   seed_fn=kg.instance_seed)
+    log("bench: saturation step, %d requests at %.0f req/s" % (len(sat), sat_rate))
+    _, s2 = serve.run_stream(srv, sat, warmup_s=min(1.0, sat_seconds / 4))
+    del srv
+    torch.cuda.empty_cache()
+    return {"workload": "Poisson %.0f req/s for %.0f s (first %.0f s excluded), G(n,m)/G(n,p) equal mix, n "
+                        "log-uniform [2^12,2^24], mean degree uniform [4,32], %.0f GB budget, %d streams"
+                        % (args.rate, duration, warmup_s, args.budget_gb, args.streams),
+            "edges_per_s": st["edges_per_s"], "p50_s": st["p50_s"], "p99_s": st["p99_s"],
+            "requests": st["requests"], "rejected": st["rejected"], "verified": st["verified"],
+            "checked_alone": st["checked_alone"], "verify_failures": st["verify_failures"],
+            "saturation": {"rate_per_s": sat_rate, "seconds": sat_seconds, "edges_per_s": s2["edges_per_s"],
+                           "p50_s": s2["p50_s"], "p99_s": s2["p99_s"], "requests": s2["requests"]}}
 
 
 def run_serve(args):
@@ -635,7 +697,8 @@ def run_serve(args):
     stream = workloads.request_stream(rate_per_s=args.rate, duration_s=args.duration, base_seed=1,
                                       seed_fn=kg.instance_seed)
     log("bench: serving %d requests over %.0f s at %.0f req/s" % (len(stream), args.duration, args.rate))
-    srv = serve.Server(budget_bytes=int(args.budget_gb * 1e9), streams=args.streams, max_batch=args.max_batch)
+    srv = serve.Server(budget_bytes=int(args.budget_gb * 1e9), streams=args.streams, max_batch=args.max_batch,
+                       verify=args.verify)
     # warm up the library and allocator
     w = workloads.request_stream(rate_per_s=200.0, duration_s=0.5, base_seed=99, seed_fn=kg.instance_seed)
     serve.run_stream(srv, w, warmup_s=0.0)
@@ -691,6 +754,12 @@ def main():
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--no-tune", action="store_true", help="batch mode: keep the default launch shapes")
     ap.add_argument("--sweep", action="store_true", help="serve mode: also sweep the arrival rate up to saturation")
+    ap.add_argument("--verify", action="store_true", help="serve mode: client checks on the device")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain mode: leave out the batched and served sub-records of the default line")
+    ap.add_argument("--extras-serve-seconds", type=float, default=20.0)
+    ap.add_argument("--extras-sat-rate", type=float, default=16000.0)
+    ap.add_argument("--extras-sat-seconds", type=float, default=5.0)
     ap.add_argument("--sweep-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a kernel of known traffic for "
@@ -738,6 +807,27 @@ def main():
         return
     desc = WORKLOADS[args.workload]
     res = run_plain(args, desc)
+    if not args.no_extras and args.workload == "gnm_undirected_n26_m31":
+        # the other two parts of the metric: batched (4096 instances as one
+        # job) and served (continuous batching of a request stream)
+        import copy
+        import torch
+        bargs = copy.copy(args)
+        bargs.steps, bargs.warmup = 2, 1
+        torch.cuda.empty_cache()
+        b = run_batch(bargs)
+        torch.cuda.empty_cache()
+        res["batched"] = {"workload": b["config"]["workload"], "instances": b["config"]["instances"],
+                          "edges_per_step": b["config"]["edges_per_step"], "waves": b["config"]["waves"],
+                          "edges_per_s": b["value"], "ms_per_step": b["ms_per_step"],
+                          "ratio_plain_to_batched": res["value"] / b["value"],
+                          "eager_kg_batch_edges_per_s": b["graphs"]["eager_kg_batch_edges_per_s"],
+                          "sampler_frac_of_hbm_peak": b["roofline"]["frac"], "tuning": b["tuning"],
+                          "batching_gain": b["batching"]}
+        sv = served_summary(args, args.extras_serve_seconds, min(3.0, args.extras_serve_seconds / 4),
+                            args.extras_sat_rate, args.extras_sat_seconds)
+        sv["ratio_plain_to_saturated"] = res["value"] / sv["saturation"]["edges_per_s"]
+        res["served"] = sv
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host (%.0f s budget)" % args.cpu_seconds)
         res["cpu_baseline"] = cpu_baseline(desc, args.cpu_seconds)

@@ -28,9 +28,16 @@
  *     errors are returned synchronously and then nothing is enqueued.
  *   - Scratch: each generation call takes a device workspace of at least the
  *     size kg_workspace_bytes() reports.  Passing d_workspace = NULL makes the
- *     library take it from the stream-ordered allocator (hipMallocAsync /
- *     hipFreeAsync on `stream`).  Two calls in flight at once must not share
- *     a workspace.
+ *     library use the workspace registered for the current device with
+ *     kg_set_workspace, or, if none is, take it from the stream-ordered
+ *     allocator (hipMallocAsync / hipFreeAsync on `stream`).  Two calls in
+ *     flight at once must not share a workspace.
+ *   - Output capacity: G(n,m) checks it on the host (KG_ENOSPC, nothing
+ *     enqueued).  Where the edge total is only known on the device (G(n,p),
+ *     views, the skip sampler, geometric graphs) an undersized output is
+ *     detected there: nothing is written to the edge buffer, the call still
+ *     returns KG_OK (it returns before the kernels run) and the required
+ *     total is stored at d_total, which the caller reads in stream order.
  *   - Statuses are returned, never thrown across the ABI.
  */
 #ifndef KG_H
@@ -75,6 +82,17 @@ const char *kg_strerror(kg_status st);
 
 /* Device workspace needed by a call on `count` instances.  Host only. */
 kg_status kg_workspace_bytes(const kg_instance *inst, uint32_t count, uint64_t *bytes);
+
+/* Register a caller-owned device buffer (256-byte aligned, `workspace_bytes`
+ * long) as the workspace of the current device: every later call on that
+ * device that passes d_workspace = NULL uses it instead of the
+ * stream-ordered allocator, and fails with KG_ENOSPC if it is smaller than
+ * the call needs.  kg_set_workspace(NULL, 0) removes the registration.  The
+ * library never frees the buffer; the caller keeps it alive while it is
+ * registered.  Calls that use the registered buffer must not overlap in
+ * time (issue them on one stream).  KG_EINVAL for NULL with a nonzero size,
+ * a zero size or a misaligned pointer; KG_EDEVICE if no device is current. */
+kg_status kg_set_workspace(void *d_workspace, uint64_t workspace_bytes);
 
 /* G(n,m) (Sec. 4.1 directed, Sec. 4.2 undirected): writes exactly m edges to
  * d_edges (room for capacity_edges pairs).  KG_ENOSPC if capacity < m. */
@@ -171,16 +189,28 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
  * workspace and enqueues kernels only: no allocation, no host copy, no
  * synchronisation.  It must be given the same list (h_inst is read on the
  * host for the launch sizes) and a workspace that the upload filled and that
- * nothing else has used since; while `stream` is capturing, the library must
- * already have been used once on the device (any call) and every call but
- * kg_batch_launch, kg_gnm, kg_gnp and kg_chunk_counts with a caller
- * workspace is refused (KG_EINVAL).  A replayed graph rewrites the same bytes;
- * replays that overlap in time must not share the arena or the workspace. */
+ * nothing else has used since.  While `stream` is capturing, the library must
+ * already have been used once on the device (any call), and only these calls
+ * are accepted, each with a caller workspace (passed, or registered with
+ * kg_set_workspace): kg_batch_launch, kg_gnm, kg_gnp, kg_pe_view,
+ * kg_chunk_counts, kg_gnp_skip, kg_rgg2d and kg_eval; the others return
+ * KG_EINVAL before enqueuing anything.  A replayed graph rewrites the same
+ * bytes; replays that overlap in time must not share the arena or the
+ * workspace. */
 kg_status kg_batch_upload(const kg_instance *h_inst, uint32_t count, void *d_workspace,
                           uint64_t workspace_bytes, void *stream);
 kg_status kg_batch_launch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
                           uint64_t arena_edges, uint64_t *d_inst_offsets,
                           void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Order-independent 64-bit checksum of an edge list, for a consumer (the
+ * serving client) that checks what it received without copying it to the
+ * host: *d_hash = sum over i < n_edges of mix(i * 0x9E3779B97F4A7C15 +
+ * (u_i << 32 | v_i)) mod 2^64, mix being the SplitMix64 finaliser.  d_edges
+ * is device memory, 8-byte aligned (any edge of a list the library wrote),
+ * d_hash one device uint64 (8-byte aligned).  Asynchronous on `stream`; kernels only, so it may be recorded
+ * into a graph. */
+kg_status kg_edge_hash(const uint32_t *d_edges, uint64_t n_edges, uint64_t *d_hash, void *stream);
 
 /* Per-instance seed of a batch drawn from a base seed: the Philox4x32-10
  * image of counter (0, i, 0, 6) under key `base`, words (w1:w0). Host only. */

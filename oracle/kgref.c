@@ -831,28 +831,41 @@ int64_t kgref_chunk_edges_given(const kgref_inst *I, uint64_t c, uint64_t Kc, ui
     if (Kc == 0) return 0;
     if (Kc > Nc) return KGREF_EINVAL;
     uint64_t *tc = (uint64_t *)malloc(T * sizeof(uint64_t));
-    uint64_t maxk = 0;
+    uint64_t *toff = (uint64_t *)malloc((T + 1) * sizeof(uint64_t));
     kgref_tile_counts(I, c, Kc, tc);
-    for (uint64_t t = 0; t < T; t++) if (tc[t] > maxk) maxk = tc[t];
-    uint64_t *keys = (uint64_t *)malloc((maxk + 1) * sizeof(uint64_t));
+    toff[0] = 0;
+    for (uint64_t t = 0; t < T; t++) toff[t + 1] = toff[t] + tc[t];
     chunk_geo g;
     chunk_geometry(I, c, &g);
-    uint64_t o = 0;
-    for (uint64_t t = 0; t < T; t++) {
+    int err = 0;
+    /* Tiles are independent given their counts: a chunk with many tiles
+     * that is generated alone spreads them over threads (each tile still
+     * writes at its own offset, so the order of the work does not matter). */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8) reduction(| : err) if (T >= 256 && !omp_in_parallel())
+#endif
+    for (int64_t ti = 0; ti < (int64_t)T; ti++) {
+        uint64_t t = (uint64_t)ti;
         uint64_t St = tile_range_slots(t, t + 1, s, Nc);
+        uint64_t *keys = (uint64_t *)malloc((tc[t] + 1) * sizeof(uint64_t));
         int st = kgref_leaf(tc[t], St, I->seed, (uint32_t)c, (uint32_t)t, keys);
-        if (st) { free(tc); free(keys); return st; }
-        for (uint64_t e = 0; e < tc[t]; e++) {
-            uint32_t u, v;
-            decode(&g, (t << s) + keys[e], &u, &v);
-            out[2 * o] = u;
-            out[2 * o + 1] = v;
-            o++;
+        if (st) {
+            err |= 1;
+        } else {
+            uint64_t o = toff[t];
+            for (uint64_t e = 0; e < tc[t]; e++, o++) {
+                uint32_t u, v;
+                decode(&g, (t << s) + keys[e], &u, &v);
+                out[2 * o] = u;
+                out[2 * o + 1] = v;
+            }
         }
+        free(keys);
     }
+    uint64_t total = toff[T];
     free(tc);
-    free(keys);
-    return (int64_t)o;
+    free(toff);
+    return err ? KGREF_EINVAL : (int64_t)total;
 }
 
 int64_t kgref_chunk_edges(const kgref_inst *I, uint64_t c, uint32_t *out)

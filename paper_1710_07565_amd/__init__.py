@@ -72,11 +72,44 @@ def workspace_bytes(instances):
     return out.value
 
 
-def _workspace(instances, workspace, device):
+def _sync(stream, device):
+    """Wait for `stream` (None: the device's current stream) before a host read."""
+    torch = _torch()
+    if stream is None:
+        torch.cuda.current_stream(device).synchronize()
+    elif hasattr(stream, "synchronize"):
+        stream.synchronize()
+    else:
+        torch.cuda.synchronize(device)
+
+
+def _on(stream):
+    """Context in which temporaries are allocated on the stream the library
+    call runs on, so the caching allocator does not hand them out again
+    while that stream still uses them."""
+    torch = _torch()
+    import contextlib
+    if stream is None or not hasattr(stream, "cuda_stream") or not isinstance(stream, torch.cuda.Stream):
+        return contextlib.nullcontext()
+    return torch.cuda.stream(stream)
+
+
+def set_workspace(workspace):
+    """Register a device uint8 tensor as the current device's workspace for
+    calls given none (kg_set_workspace); None removes the registration.  The
+    caller keeps the tensor alive while it is registered."""
+    if workspace is None:
+        _lib.check(_lib.lib().kg_set_workspace(None, 0), "kg_set_workspace")
+    else:
+        _lib.check(_lib.lib().kg_set_workspace(workspace.data_ptr(), workspace.numel()), "kg_set_workspace")
+
+
+def _workspace(instances, workspace, device, stream=None):
     torch = _torch()
     need = workspace_bytes(instances)
     if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+        with _on(stream):
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
     if workspace.numel() < need:
         raise KgError(_lib.KG_ENOSPC, "workspace")
     return workspace, need
@@ -87,9 +120,10 @@ def gnm(n, m, directed=True, seed=1, chunks=1, out=None, workspace=None, stream=
     tensor of edges on the device, in canonical chunk order."""
     torch = _torch()
     if out is None:
-        out = torch.empty((max(int(m), 0), 2), dtype=torch.uint32, device=device)
+        with _on(stream):
+            out = torch.empty((max(int(m), 0), 2), dtype=torch.uint32, device=device)
     inst = Instance(n, GNM, directed, m, 0.0, seed, chunks)
-    ws, need = _workspace([inst], workspace, out.device)
+    ws, need = _workspace([inst], workspace, out.device, stream)
     st = _lib.lib().kg_gnm(int(n), int(m), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
                            out.data_ptr() if out.numel() else None, out.shape[0], ws.data_ptr(), ws.numel(),
                            _stream(stream))
@@ -101,7 +135,7 @@ def gnp_count(n, p, directed=True, seed=1, chunks=1, workspace=None, stream=None
     """Edge total of G(n,p) (synchronises the stream)."""
     import ctypes
     inst = Instance(n, GNP, directed, 0, p, seed, chunks)
-    ws, need = _workspace([inst], workspace, device)
+    ws, need = _workspace([inst], workspace, device, stream)
     tot = ctypes.c_uint64(0)
     st = _lib.lib().kg_gnp_count(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
                                  ctypes.byref(tot), ws.data_ptr(), ws.numel(), _stream(stream))
@@ -119,10 +153,12 @@ def gnp(n, p, directed=True, seed=1, chunks=1, out=None, total=None, workspace=N
     sized = out is None
     if sized:
         E = gnp_count(n, p, directed, seed, chunks, workspace=workspace, stream=stream, device=device)
-        out = torch.empty((E, 2), dtype=torch.uint32, device=device)
+        with _on(stream):
+            out = torch.empty((E, 2), dtype=torch.uint32, device=device)
     if total is None:
-        total = torch.zeros(1, dtype=torch.uint64, device=out.device)
-    ws, need = _workspace([inst], workspace, out.device)
+        with _on(stream):
+            total = torch.zeros(1, dtype=torch.uint64, device=out.device)
+    ws, need = _workspace([inst], workspace, out.device, stream)
     st = _lib.lib().kg_gnp(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
                            out.data_ptr() if out.numel() else None, out.shape[0], total.data_ptr(),
                            ws.data_ptr(), ws.numel(), _stream(stream))
@@ -137,8 +173,9 @@ def chunk_counts(inst, workspace=None, stream=None, device="cuda"):
     torch = _torch()
     from . import _lib as L
     C = inst.chunks if inst.directed else inst.chunks * (inst.chunks + 1) // 2
-    out = torch.empty(C, dtype=torch.uint64, device=device)
-    ws, need = _workspace([inst], workspace, device)
+    with _on(stream):
+        out = torch.empty(C, dtype=torch.uint64, device=device)
+    ws, need = _workspace([inst], workspace, device, stream)
     st = L.lib().kg_chunk_counts(inst.c(), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
     L.check(st, "kg_chunk_counts")
     return out
@@ -160,10 +197,12 @@ def batch(instances, arena=None, offsets=None, workspace=None, stream=None, devi
                 total += gnp_count(i.n, i.p, i.directed, i.seed, i.chunks, stream=stream, device=device)
             else:
                 total += view_count(i, stream=stream, device=device)
-        arena = torch.empty((total, 2), dtype=torch.uint32, device=device)
+        with _on(stream):
+            arena = torch.empty((total, 2), dtype=torch.uint32, device=device)
     if offsets is None:
-        offsets = torch.empty(cnt + 1, dtype=torch.uint64, device=arena.device)
-    ws, need = _workspace(instances, workspace, arena.device)
+        with _on(stream):
+            offsets = torch.empty(cnt + 1, dtype=torch.uint64, device=arena.device)
+    ws, need = _workspace(instances, workspace, arena.device, stream)
     st = _lib.lib().kg_batch(arr, cnt, arena.data_ptr() if arena.numel() else None, arena.shape[0],
                              offsets.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
     _lib.check(st, "kg_batch")
@@ -174,13 +213,13 @@ def view_count(inst, workspace=None, stream=None, device="cuda"):
     """Edges of one instance (whole graph or view) from a counting pass
     (kg_batch with an empty arena; synchronises the stream)."""
     torch = _torch()
-    offs = torch.empty(2, dtype=torch.uint64, device=device)
-    empty = torch.empty((0, 2), dtype=torch.uint32, device=device)
-    ws, need = _workspace([inst], workspace, device)
+    with _on(stream):
+        offs = torch.empty(2, dtype=torch.uint64, device=device)
+    ws, need = _workspace([inst], workspace, device, stream)
     arr = (KgInstance * 1)(inst.c())
     _lib.check(_lib.lib().kg_batch(arr, 1, None, 0, offs.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
                "kg_batch")
-    torch.cuda.current_stream(device).synchronize() if stream is None else stream.synchronize()
+    _sync(stream, device)
     return int(offs.view(torch.int64)[1].item())
 
 
@@ -197,11 +236,13 @@ def pe_view(n, rank, chunks, directed=True, m=0, p=None, seed=1, out=None, total
     view = Instance(n, model, directed, inst.m, inst.p, seed, chunks, view=int(rank) + 1)
     sized = out is None
     if sized:
-        out = torch.empty((view_count(view, workspace=workspace, stream=stream, device=device), 2),
-                          dtype=torch.uint32, device=device)
+        E = view_count(view, workspace=workspace, stream=stream, device=device)
+        with _on(stream):
+            out = torch.empty((E, 2), dtype=torch.uint32, device=device)
     if total is None:
-        total = torch.zeros(1, dtype=torch.uint64, device=out.device)
-    ws, need = _workspace([view], workspace, out.device)
+        with _on(stream):
+            total = torch.zeros(1, dtype=torch.uint64, device=out.device)
+    ws, need = _workspace([view], workspace, out.device, stream)
     st = _lib.lib().kg_pe_view(inst.c(), int(rank), out.data_ptr() if out.numel() else None, out.shape[0],
                                total.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
     _lib.check(st, "kg_pe_view")
@@ -217,16 +258,19 @@ def gnp_skip(n, p, directed=True, seed=1, chunks=1, out=None, total=None, worksp
     `out`, returns (out, total) as gnp() does."""
     torch = _torch()
     inst = Instance(n, GNP, directed, 0, p, seed, chunks)
-    ws, need = _workspace([inst], workspace, device if out is None else out.device)
-    if total is None:
-        total = torch.zeros(1, dtype=torch.uint64, device=ws.device)
+    with _on(stream):
+        ws, need = _workspace([inst], workspace, device if out is None else out.device)
+        if total is None:
+            total = torch.zeros(1, dtype=torch.uint64, device=ws.device)
     sized = out is None
     if sized:
         st = _lib.lib().kg_gnp_skip(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
                                     None, 0, total.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
         _lib.check(st, "kg_gnp_skip")
+        _sync(stream, ws.device)
         E = int(total.view(torch.int64).cpu()[0])
-        out = torch.empty((E, 2), dtype=torch.uint32, device=ws.device)
+        with _on(stream):
+            out = torch.empty((E, 2), dtype=torch.uint32, device=ws.device)
     st = _lib.lib().kg_gnp_skip(int(n), float(p), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
                                 out.data_ptr() if out.numel() else None, out.shape[0], total.data_ptr(),
                                 ws.data_ptr(), ws.numel(), _stream(stream))
@@ -262,12 +306,13 @@ def rgg2d(n, r, seed=1, points=None, out=None, total=None, workspace=None, strea
     total exceeds out.shape[0] nothing is written to `out`."""
     torch = _torch()
     dev = out.device if out is not None else (points.device if points is not None else torch.device(device))
-    if points is None:
-        points = torch.empty((int(n), 2), dtype=torch.float64, device=dev)
-    if workspace is None:
-        workspace = torch.empty(max(rgg2d_workspace_bytes(n, r), 1), dtype=torch.uint8, device=dev)
-    if total is None:
-        total = torch.zeros(1, dtype=torch.uint64, device=dev)
+    with _on(stream):
+        if points is None:
+            points = torch.empty((int(n), 2), dtype=torch.float64, device=dev)
+        if workspace is None:
+            workspace = torch.empty(max(rgg2d_workspace_bytes(n, r), 1), dtype=torch.uint8, device=dev)
+        if total is None:
+            total = torch.zeros(1, dtype=torch.uint64, device=dev)
 
     def call(edges):
         st = _lib.lib().kg_rgg2d(int(n), float(r), int(seed) & (2**64 - 1),
@@ -283,11 +328,14 @@ def rgg2d(n, r, seed=1, points=None, out=None, total=None, workspace=None, strea
     mu = rgg2d_expected_edges(int(n), float(r))
     cap = int(min(n * (n - 1) // 2, mu * 1.05 + 8.0 * math.sqrt(mu + 1.0) * max(1.0, math.sqrt(n * r * r * 10.0))
                   + 1024))
-    edges = torch.empty((max(cap, 0), 2), dtype=torch.uint32, device=dev)
+    with _on(stream):
+        edges = torch.empty((max(cap, 0), 2), dtype=torch.uint32, device=dev)
     call(edges)
+    _sync(stream, dev)
     E = int(total.view(torch.int64).cpu()[0])
     if E > edges.shape[0]:
-        edges = torch.empty((E, 2), dtype=torch.uint32, device=dev)
+        with _on(stream):
+            edges = torch.empty((E, 2), dtype=torch.uint32, device=dev)
         call(edges)
     return points, edges[:E]
 
@@ -341,6 +389,20 @@ def eval_device(fn, d_in, n, out_dtype, out_width, stream=None):
     out = torch.empty((int(n), out_width), dtype=out_dtype, device=d_in.device)
     st = _lib.lib().kg_eval(int(fn), d_in.data_ptr(), out.data_ptr(), int(n), _stream(stream))
     _lib.check(st, "kg_eval")
+    return out
+
+
+def edge_hash(edges, out=None, stream=None):
+    """Order-independent 64-bit checksum of an (E, 2) uint32 edge tensor on
+    the device (kg_edge_hash); returns a one-element device uint64 tensor,
+    asynchronously on `stream`."""
+    torch = _torch()
+    if out is None:
+        with _on(stream):
+            out = torch.empty(1, dtype=torch.uint64, device=edges.device)
+    st = _lib.lib().kg_edge_hash(edges.data_ptr() if edges.numel() else None, int(edges.shape[0]),
+                                 out.data_ptr(), _stream(stream))
+    _lib.check(st, "kg_edge_hash")
     return out
 
 

@@ -15,6 +15,7 @@
 #include "kg_tile.hpp"
 #include "kg_skip.hpp"
 #include "kg_rgg.hpp"
+#include "kg_hash.hpp"
 
 namespace kg {
 __device__ double g_lnf_tab[kLnfTab + 1];
@@ -70,6 +71,43 @@ struct KernelTimer {
 std::mutex g_init_mu;
 bool g_init_done[64];
 int g_num_cu[64];
+
+// Workspaces registered with kg_set_workspace, per device: calls given no
+// workspace of their own use it instead of a stream-ordered allocation.
+std::mutex g_ws_mu;
+void *g_reg_ws[64];
+uint64_t g_reg_bytes[64];
+
+// A call that passes no workspace gets the one registered for the current
+// device, if any (d_ws and bytes are left alone otherwise).
+void registered_workspace(void *&d_ws, uint64_t &bytes)
+{
+    if (d_ws) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (g_reg_ws[dev]) {
+        d_ws = g_reg_ws[dev];
+        bytes = g_reg_bytes[dev];
+    }
+}
+
+// While `s` is being recorded into a graph a call may enqueue kernels only:
+// the library must already be set up on the device (the first call launches
+// a table kernel and synchronises) and the workspace must not come from the
+// stream-ordered allocator.
+kg_status capture_check(hipStream_t s, const void *d_ws)
+{
+    if (!capturing(s)) return KG_OK;
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return KG_EDEVICE;
+    bool ready;
+    {
+        std::lock_guard<std::mutex> lk(g_init_mu);
+        ready = g_init_done[d];
+    }
+    return ready && d_ws ? KG_OK : KG_EINVAL;
+}
 
 int g_sample_blocks_per_cu[64];
 int g_plan_blocks_per_cu[64];
@@ -313,18 +351,12 @@ kg_status run(const kg_instance *inst, uint32_t count, uint32_t *edges, uint64_t
     kg_status st = prepare(inst, count, P);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
-    if (capturing(s)) {
-        // a graph may hold kernels only: the device must be set up, the
-        // workspace given, the descriptor table resident, nothing read back
-        int d = 0;
-        if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return KG_EDEVICE;
-        bool ready;
-        {
-            std::lock_guard<std::mutex> lk(g_init_mu);
-            ready = g_init_done[d];
-        }
-        if (!ready || !d_ws || counts_only || (count > 1 && !resident)) return KG_EINVAL;
-    }
+    registered_workspace(d_ws, ws_bytes);
+    st = capture_check(s, d_ws);
+    if (st) return st;
+    // nothing may be read back, and a batch's descriptor table must already
+    // be resident
+    if (capturing(s) && (counts_only || (count > 1 && !resident))) return KG_EINVAL;
     int dev = 0;
     st = ensure_init(&dev);
     if (st) return st;
@@ -536,7 +568,9 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
     const uint64_t nw = (P.Tb + 63) / 64;          // one wave per 64 tiles
     if (nw > 0x7FFFFFFFull || nw > P.Tb + 1) return KG_ERANGE;
     hipStream_t s = (hipStream_t)stream;
-    if (capturing(s) && !d_workspace) return KG_EINVAL;
+    registered_workspace(d_workspace, workspace_bytes);
+    st = capture_check(s, d_workspace);
+    if (st) return st;
     int dev = 0;
     st = ensure_init(&dev);
     if (st) return st;
@@ -586,7 +620,9 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
     if (((uintptr_t)d_points & 15) != 0 || ((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
     if (!d_edges) capacity_edges = 0;
     hipStream_t s = (hipStream_t)stream;
-    if (capturing(s) && !d_workspace) return KG_EINVAL;
+    registered_workspace(d_workspace, workspace_bytes);
+    st = capture_check(s, d_workspace);
+    if (st) return st;
     int dev = 0;
     st = ensure_init(&dev);
     if (st) return st;
@@ -681,6 +717,33 @@ kg_status kg_batch_launch(const kg_instance *h_inst, uint32_t count, uint32_t *d
                stream, false, nullptr, nullptr, true);
 }
 
+kg_status kg_edge_hash(const uint32_t *d_edges, uint64_t n_edges, uint64_t *d_hash, void *stream)
+{
+    if (!d_hash || (n_edges > 0 && !d_edges)) return KG_EINVAL;
+    if (((uintptr_t)d_edges & 7) != 0 || ((uintptr_t)d_hash & 7) != 0) return KG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KG_EDEVICE;
+    hipLaunchKernelGGL(hash_clear_kernel, dim3(1), dim3(64), 0, s, d_hash);
+    uint64_t grid = (n_edges / 2 + 255) / 256;
+    if (grid < 1) grid = 1;
+    if (grid > 2048) grid = 2048;
+    hipLaunchKernelGGL(hash_kernel, dim3((uint32_t)grid), dim3(256), 0, s, d_edges, n_edges, d_hash);
+    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+}
+
+kg_status kg_set_workspace(void *d_workspace, uint64_t workspace_bytes)
+{
+    if (!d_workspace && workspace_bytes != 0) return KG_EINVAL;
+    if (d_workspace && (workspace_bytes == 0 || ((uintptr_t)d_workspace & 255) != 0)) return KG_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KG_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_reg_ws[dev] = d_workspace;
+    g_reg_bytes[dev] = workspace_bytes;
+    return KG_OK;
+}
+
 uint64_t kg_instance_seed(uint64_t base, uint32_t i)
 {
     const U4 w = philox(0, i, 0, TAG_INST, (uint32_t)base, (uint32_t)(base >> 32));
@@ -740,8 +803,10 @@ kg_status kg_eval(int fn, const void *d_in, void *d_out, uint64_t n, void *strea
     if (fn < KG_EVAL_PHILOX || fn > KG_EVAL_SQRT_DIV) return KG_EINVAL;
     if (n == 0) return KG_OK;
     if (!d_in || !d_out) return KG_EINVAL;
+    kg_status st = capture_check((hipStream_t)stream, d_in);
+    if (st) return st;
     int dev = 0;
-    const kg_status st = ensure_init(&dev);
+    st = ensure_init(&dev);
     if (st) return st;
     const uint64_t nb = (n + 255) / 256;
     if (nb > 0x7FFFFFFFull) return KG_ERANGE;

@@ -13,7 +13,11 @@ its memory returns to the budget when the client releases it.
 
 The bytes of a request do not depend on what it was batched with: kg_batch
 output for an instance equals kg_gnm / kg_gnp alone (the generator is a pure
-function of the instance).
+function of the instance).  With `verify` the client checks every finished
+request on the device before releasing it: a 64-bit checksum of its edge
+list (kg_edge_hash, on the batch's stream), the edge count (exactly m for
+G(n,m)), and for a seeded sample of the requests the checksum of the same
+request generated alone.
 """
 import collections
 import threading
@@ -35,7 +39,7 @@ def _edge_bound(spec):
 
 
 class Request:
-    __slots__ = ("rid", "spec", "arrival", "admitted", "done", "edges", "offset", "batch", "nedges", "bound")
+    __slots__ = ("rid", "spec", "arrival", "admitted", "done", "edges", "offset", "batch", "nedges", "bound", "hash")
 
     def __init__(self, rid, spec, arrival):
         self.rid, self.spec, self.arrival = rid, spec, arrival
@@ -43,6 +47,7 @@ class Request:
         self.edges = None
         self.offset = self.nedges = None
         self.batch = None
+        self.hash = None
         self.bound = _edge_bound(spec)
 
 
@@ -90,7 +95,8 @@ class Server:
                  (the client's check), before an automatic release
     """
 
-    def __init__(self, budget_bytes, streams=4, max_batch=256, keep=False, on_done=None, device="cuda"):
+    def __init__(self, budget_bytes, streams=4, max_batch=256, keep=False, on_done=None, device="cuda",
+                 verify=False, alone_every=100):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -113,6 +119,13 @@ class Server:
         self.ranges = _Ranges(self.arena_edges)
         self.ws = [None] * streams
         self.offsets = [torch.empty(max_batch + 1, dtype=torch.uint64, device=self.device) for _ in range(streams)]
+        # client-side checks on the device (checksums, a sample re-generated alone)
+        self.verify = verify
+        self.alone_every = int(alone_every)
+        self.verifying = []
+        self.verified = 0
+        self.checked_alone = 0
+        self.verify_failures = []
 
     # -- client side -------------------------------------------------------
     def submit(self, spec, arrival=None):
@@ -214,10 +227,69 @@ class Server:
                 self.finished.append(r)
                 if self.on_done is not None:
                     self.on_done(r)
-            if not self.keep:
+            if self.verify:
+                self._start_verify(b)
+            elif not self.keep:
                 for r in b.reqs:
                     self.release(r)
         self.inflight = still
+        if self.verify:
+            self._finish_verify()
+
+    # -- the client's checks -------------------------------------------------
+    def _sampled(self, r):
+        return self.alone_every > 0 and (r.spec.seed * 0x9E3779B97F4A7C15 >> 7) % self.alone_every == 0
+
+    def _start_verify(self, b):
+        """Enqueue the checksums of a finished batch's requests on its stream
+        (and, for sampled requests, the request generated alone and its
+        checksum); the ranges stay reserved until those kernels are done."""
+        from . import edge_hash, gnm, gnp, workspace_bytes
+        torch = self.torch
+        alone = []
+        with torch.cuda.stream(b.stream):
+            h = torch.empty(len(b.reqs), dtype=torch.uint64, device=self.device)
+            for i, r in enumerate(b.reqs):
+                edge_hash(r.edges, out=h[i:i + 1], stream=b.stream)
+            for i, r in enumerate(b.reqs):
+                if not self._sampled(r):
+                    continue
+                s = r.spec
+                inst = Instance(s.n, s.model, s.directed, s.m, s.p, s.seed, s.chunks)
+                buf = torch.empty((max(r.nedges, 1), 2), dtype=torch.uint32, device=self.device)
+                ws = torch.empty(max(workspace_bytes([inst]), 1), dtype=torch.uint8, device=self.device)
+                if s.model == GNM:
+                    gnm(s.n, s.m, s.directed, s.seed, s.chunks, out=buf, workspace=ws, stream=b.stream)
+                else:
+                    tot = torch.zeros(1, dtype=torch.uint64, device=self.device)
+                    gnp(s.n, s.p, s.directed, s.seed, s.chunks, out=buf, total=tot, workspace=ws, stream=b.stream)
+                ha = edge_hash(buf[:r.nedges], stream=b.stream)
+                alone.append((i, ha, buf, ws))
+            ev = torch.cuda.Event()
+            ev.record(b.stream)
+        self.verifying.append((b, h, alone, ev))
+
+    def _finish_verify(self):
+        still = []
+        for item in self.verifying:
+            b, h, alone, ev = item
+            if not ev.query():
+                still.append(item)
+                continue
+            hv = h.view(self.torch.int64).cpu().tolist()
+            for i, r in enumerate(b.reqs):
+                r.hash = hv[i] & (2**64 - 1)
+                if r.spec.model == GNM and r.nedges != r.spec.m:
+                    self.verify_failures.append((r.rid, "edge count"))
+            for i, ha, _, _ in alone:
+                self.checked_alone += 1
+                if (int(ha.view(self.torch.int64).item()) & (2**64 - 1)) != b.reqs[i].hash:
+                    self.verify_failures.append((b.reqs[i].rid, "checksum differs from the request alone"))
+            self.verified += len(b.reqs)
+            if not self.keep:
+                for r in b.reqs:
+                    self.release(r)
+        self.verifying = still
 
     def step(self):
         """One scheduler tick: reap finished launches, admit and launch."""
@@ -230,7 +302,7 @@ class Server:
 
     def drain(self, timeout=600.0):
         t0 = time.perf_counter()
-        while (self.queue or self.inflight) and time.perf_counter() - t0 < timeout:
+        while (self.queue or self.inflight or self.verifying) and time.perf_counter() - t0 < timeout:
             if not self.step():
                 time.sleep(0.0002)
         self._reap()
@@ -243,13 +315,17 @@ def run_stream(server, stream, warmup_s=5.0, progress=None):
     reqs = []
     i = 0
     last = t0
-    while i < len(stream) or server.queue or server.inflight:
+    while i < len(stream) or server.queue or server.inflight or server.verifying:
         now = time.perf_counter() - t0
         while i < len(stream) and stream[i][0] <= now:
             reqs.append(server.submit(stream[i][1], arrival=t0 + stream[i][0]))
             i += 1
-        if not server.step():
-            time.sleep(0.0001)
+        if not server.step() and not server.inflight and not server.verifying:
+            # idle: sleep until the next arrival, in short slices
+            if i < len(stream):
+                gap = stream[i][0] - (time.perf_counter() - t0)
+                if gap > 0:
+                    time.sleep(min(gap, 0.0005))
         if progress and time.perf_counter() - last > 5.0:
             last = time.perf_counter()
             progress(now, i, len(server.queue), len(server.inflight))
@@ -264,4 +340,6 @@ def run_stream(server, stream, warmup_s=5.0, progress=None):
         return lat[min(len(lat) - 1, int(q * len(lat)))]
     return reqs, {"requests": len(reqs), "rejected": server.rejected, "edges": edges, "span_s": span,
                   "edges_per_s": edges / span if span > 0 else None, "p50_s": pct(0.50), "p99_s": pct(0.99),
-                  "measured_after_s": warmup_s, "latency_samples": len(lat)}
+                  "measured_after_s": warmup_s, "latency_samples": len(lat),
+                  "verified": server.verified, "checked_alone": server.checked_alone,
+                  "verify_failures": len(server.verify_failures)}

@@ -156,3 +156,36 @@ def test_rgg_argument_checks_and_workspace(L):
     assert L.kg_rgg2d(100, 0.1, 1, None, None, 0, None, None, 0, None) == _lib.KG_EINVAL      # no points
     assert L.kg_rgg2d(100, 0.1, 1, 8, None, 0, None, None, 0, None) == _lib.KG_EINVAL         # misaligned
     assert L.kg_rgg2d(2**32, 0.1, 1, None, None, 0, None, None, 0, None) == _lib.KG_ERANGE
+
+
+def test_set_workspace_argument_checks(L):
+    """kg_set_workspace refuses a NULL buffer with a size, a buffer without
+    one and a pointer that is not 256-byte aligned, before asking for a
+    device; removing the registration needs a current device only."""
+    from paper_1710_07565_amd import _lib
+    assert L.kg_set_workspace(None, 64) == _lib.KG_EINVAL
+    assert L.kg_set_workspace(4096, 0) == _lib.KG_EINVAL
+    assert L.kg_set_workspace(4096 + 64, 1 << 20) == _lib.KG_EINVAL
+    assert L.kg_set_workspace(None, 0) in (_lib.KG_OK, _lib.KG_EDEVICE)
+
+
+@pytest.mark.parametrize("n,m,p,directed,P,s_want", [
+    (2**16, 2**20, 0.0, True, 64, 21),                 # small directed G(n,m)
+    (2**26, 2**31, 0.0, False, 256, 29),               # headline undirected G(n,m)
+    (2**25, 0, 16.0 / (2**25 - 1), True, 2**16, 30),   # directed G(n,p), mean out-degree 16
+    (2**25, 0, 64.0 / (2**25 - 1), False, 256, 28),    # undirected G(n,p), mean degree 64
+])
+def test_tile_exponent_of_the_workloads(kgref, n, m, p, directed, P, s_want):
+    """The tile exponent of each benchmark workload, checked against the
+    sampling threshold's definition written out here: the expected samples
+    of a full tile, 2^s m / N (G(n,m)) or 2^s p (G(n,p)), reach 362 at s and
+    not at s - 1; every one of these workloads lands within 0.01 of 512."""
+    from fractions import Fraction
+    model = 0 if p == 0.0 else 1
+    I = kgref.inst(n, m=m, p=p, directed=directed, seed=1, chunks=P, model=model)
+    s = kgref.tile_exponent(I)
+    assert s == s_want
+    N = n * (n - 1) // (1 if directed else 2)
+    mean = (lambda t: Fraction(m * 2**t, N)) if model == 0 else (lambda t: Fraction(p) * 2**t)
+    assert mean(s) >= 362 and mean(s - 1) < 362
+    assert abs(float(mean(s)) - 512.0) < 0.01
