@@ -55,7 +55,9 @@ enum {
     KG_EINVAL = -1,   /* bad argument: n, m, p, P, model, NULL pointer */
     KG_ERANGE = -2,   /* outside the limits above */
     KG_ENOSPC = -3,   /* output or workspace too small; nothing enqueued */
-    KG_EDEVICE = -4   /* a HIP call failed */
+    KG_EDEVICE = -4,  /* a HIP call failed */
+    KG_ESCRATCH = -5  /* kg_gnm_static: the instance needs more workspace than
+                       * KG_STATIC_SCRATCH_BYTES; nothing enqueued */
 };
 enum { KG_GNM = 0, KG_GNP = 1 };
 
@@ -99,6 +101,24 @@ kg_status kg_set_workspace(void *d_workspace, uint64_t workspace_bytes);
 kg_status kg_gnm(uint64_t n, uint64_t m, int directed, uint64_t seed, uint32_t chunks,
                  uint32_t *d_edges, uint64_t capacity_edges,
                  void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* kg_gnm for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call the allocator, harnesses
+ * that forbid it).  Same arguments, checks and output bytes as kg_gnm, but the
+ * workspace is a static scratch area of KG_STATIC_SCRATCH_BYTES (96 MiB) in
+ * the library, one per device, held from the library's first call on that
+ * device until the process ends; the call itself allocates nothing (no
+ * hipMalloc, no stream-ordered allocation, no heap).  An instance whose
+ * workspace (kg_workspace_bytes) exceeds that size returns KG_ESCRATCH before
+ * anything is enqueued; the headline size (undirected n = 2^26, m = 2^31,
+ * P = 256) needs 65.3 MiB.  Every call on one device shares that device's
+ * area, so calls on one device that overlap in time race: issue them on one
+ * stream.  The library's first call on a device (any entry point) sets the
+ * device up and synchronises; under stream capture that first call must
+ * already have happened. */
+#define KG_STATIC_SCRATCH_BYTES (96ull << 20)
+kg_status kg_gnm_static(uint64_t n, uint64_t m, int directed, uint64_t seed, uint32_t chunks,
+                        uint32_t *d_edges, uint64_t capacity_edges, void *stream);
 
 /* G(n,p) (Sec. 4.3: binomial chunk counts keyed by chunk id, then the G(n,m)
  * sampler per chunk).  The edge total is stored at the device address

@@ -131,6 +131,20 @@ def gnm(n, m, directed=True, seed=1, chunks=1, out=None, workspace=None, stream=
     return out[:m]
 
 
+def gnm_static(n, m, directed=True, seed=1, chunks=1, out=None, stream=None, device="cuda"):
+    """G(n,m) through kg_gnm_static: the library's static per-device scratch
+    is the workspace, so the call allocates nothing but `out` (if not given).
+    Same bytes as gnm()."""
+    torch = _torch()
+    if out is None:
+        with _on(stream):
+            out = torch.empty((max(int(m), 0), 2), dtype=torch.uint32, device=device)
+    st = _lib.lib().kg_gnm_static(int(n), int(m), int(bool(directed)), int(seed) & (2**64 - 1), int(chunks),
+                                  out.data_ptr() if out.numel() else None, out.shape[0], _stream(stream))
+    _lib.check(st, "kg_gnm_static")
+    return out[:m]
+
+
 def gnp_count(n, p, directed=True, seed=1, chunks=1, workspace=None, stream=None, device="cuda"):
     """Edge total of G(n,p) (synchronises the stream)."""
     import ctypes

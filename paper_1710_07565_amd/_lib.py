@@ -6,14 +6,15 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("KG_LIBRARY") or os.path.join(HERE, "libkg.so")
 
-KG_OK, KG_EINVAL, KG_ERANGE, KG_ENOSPC, KG_EDEVICE = 0, -1, -2, -3, -4
+KG_OK, KG_EINVAL, KG_ERANGE, KG_ENOSPC, KG_EDEVICE, KG_ESCRATCH = 0, -1, -2, -3, -4, -5
+KG_STATIC_SCRATCH_BYTES = 96 << 20
 KG_GNM, KG_GNP = 0, 1
 KG_OPT_LEAF_CAP, KG_OPT_SAMPLE_WAVES, KG_OPT_PLAN_WAVES = 1, 2, 3
 
 EXPORTS = ["kg_spec_version", "kg_strerror", "kg_workspace_bytes", "kg_set_workspace", "kg_gnm", "kg_gnp", "kg_gnp_count",
            "kg_chunk_counts", "kg_batch", "kg_batch_upload", "kg_batch_launch", "kg_pe_view", "kg_gnp_skip",
            "kg_rgg2d_workspace_bytes", "kg_rgg2d", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_eval",
-           "kg_kernel_time_read", "kg_edge_hash"]
+           "kg_kernel_time_read", "kg_edge_hash", "kg_gnm_static"]
 KG_OPT_TIME_KERNELS = 4
 KG_KERNEL_COUNT, KG_KERNEL_SCAN, KG_KERNEL_PLAN, KG_KERNEL_SAMPLE, KG_KERNEL_QUEUE = 0, 1, 2, 3, 4
 KG_EVAL_PHILOX, KG_EVAL_LOG, KG_EVAL_LOG1P, KG_EVAL_LNF_DIFF, KG_EVAL_HYP, KG_EVAL_BIN, KG_EVAL_SQRT_DIV = range(1, 8)
@@ -51,6 +52,7 @@ def lib():
     L.kg_set_workspace.argtypes = [vp, u64]; L.kg_set_workspace.restype = i32
     L.kg_edge_hash.argtypes = [vp, u64, vp, vp]; L.kg_edge_hash.restype = i32
     L.kg_gnm.argtypes = [u64, u64, ctypes.c_int, u64, u32, vp, u64, vp, u64, vp]; L.kg_gnm.restype = i32
+    L.kg_gnm_static.argtypes = [u64, u64, ctypes.c_int, u64, u32, vp, u64, vp]; L.kg_gnm_static.restype = i32
     L.kg_gnp.argtypes = [u64, dbl, ctypes.c_int, u64, u32, vp, u64, vp, vp, u64, vp]; L.kg_gnp.restype = i32
     L.kg_gnp_count.argtypes = [u64, dbl, ctypes.c_int, u64, u32, ctypes.POINTER(u64), vp, u64, vp]
     L.kg_gnp_count.restype = i32

@@ -21,6 +21,12 @@ namespace kg {
 __device__ double g_lnf_tab[kLnfTab + 1];
 }
 
+// Static scratch of kg_gnm_static (KG_STATIC_SCRATCH_BYTES, kg.h): the
+// workspace of callers that cannot allocate.  Each device the library runs on holds one copy of it for the
+// life of the process.  Host code must use the device address looked up
+// with hipGetSymbolAddress (g_scratch_ptr), never the array's name.
+static __device__ __align__(256) uint8_t scratch[KG_STATIC_SCRATCH_BYTES];
+
 using namespace kg;
 
 namespace {
@@ -48,13 +54,17 @@ bool capturing(hipStream_t s)
     return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
+// Set while kg_gnm_static runs on this thread: its calls record no timer
+// events (creating and keeping them allocates).
+thread_local bool t_no_timers = false;
+
 struct KernelTimer {
     int id;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     KernelTimer(int kid, hipStream_t st) : id(kid), s(st)
     {
-        if (!g_time_kernels || capturing(s)) return;
+        if (!g_time_kernels || t_no_timers || capturing(s)) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
         (void)hipEventRecord(a, s);
     }
@@ -71,6 +81,7 @@ struct KernelTimer {
 std::mutex g_init_mu;
 bool g_init_done[64];
 int g_num_cu[64];
+void *g_scratch_ptr[64];        // device address of `scratch` on each device (set up by ensure_init)
 
 // Workspaces registered with kg_set_workspace, per device: calls given no
 // workspace of their own use it instead of a stream-ordered allocation.
@@ -130,6 +141,10 @@ kg_status ensure_init(int *dev_out)
     nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_plan_blocks_per_cu[dev] = nb;
+    // this device's copy of the static scratch (its own address per device)
+    void *sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return KG_EDEVICE;
+    g_scratch_ptr[dev] = sp;
     hipLaunchKernelGGL(lnf_init_kernel, dim3(1), dim3(64), 0, 0);
     if (hipGetLastError() != hipSuccess) return KG_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return KG_EDEVICE;
@@ -204,8 +219,26 @@ Layout layout_for(uint32_t ninst, uint64_t G, uint64_t Tb)
     return L;
 }
 
+// The planned instances of a call.  A single instance lives inside the
+// object, so a one-instance call makes no heap allocation.
+struct InstList {
+    Inst first;
+    std::vector<Inst> many;     // a batch (more than one instance)
+    uint32_t count = 0;
+    void resize(uint32_t c)
+    {
+        count = c;
+        if (c > 1) many.resize(c);
+    }
+    size_t size() const { return count; }
+    Inst *data() { return count > 1 ? many.data() : &first; }
+    const Inst *data() const { return count > 1 ? many.data() : &first; }
+    Inst &operator[](size_t i) { return data()[i]; }
+    const Inst &operator[](size_t i) const { return data()[i]; }
+};
+
 struct Prepared {
-    std::vector<Inst> insts;
+    InstList insts;
     uint64_t G = 0, Tb = 0;
     Layout L;
 };
@@ -477,6 +510,7 @@ const char *kg_strerror(kg_status st)
     case KG_ERANGE: return "argument outside the supported range";
     case KG_ENOSPC: return "output or workspace too small";
     case KG_EDEVICE: return "HIP runtime error";
+    case KG_ESCRATCH: return "the instance needs more workspace than the static scratch holds (96 MiB)";
     default: return "unknown status";
     }
 }
@@ -503,6 +537,35 @@ kg_status kg_gnm(uint64_t n, uint64_t m, int directed, uint64_t seed, uint32_t c
     if (capacity_edges < m) return KG_ENOSPC;
     return run(&I, 1, d_edges, capacity_edges, nullptr, nullptr, d_workspace, workspace_bytes, stream, false,
                nullptr, nullptr);
+}
+
+kg_status kg_gnm_static(uint64_t n, uint64_t m, int directed, uint64_t seed, uint32_t chunks, uint32_t *d_edges,
+                        uint64_t capacity_edges, void *stream)
+{
+    const kg_instance I = make_inst(n, KG_GNM, directed, m, 0.0, seed, chunks);
+    if (!d_edges && m > 0) return KG_EINVAL;
+    if (((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    Prepared P;
+    kg_status st = prepare(&I, 1, P);
+    if (st) return st;
+    if (capacity_edges < m) return KG_ENOSPC;
+    if (P.L.total > KG_STATIC_SCRATCH_BYTES) return KG_ESCRATCH;
+    // the device's scratch address is looked up once, by the set-up of the
+    // first call on the device (which, like every first call, synchronises)
+    int dev = 0;
+    st = ensure_init(&dev);
+    if (st) return st;
+    void *sp;
+    {
+        std::lock_guard<std::mutex> lk(g_init_mu);
+        sp = g_scratch_ptr[dev];
+    }
+    if (!sp) return KG_EDEVICE;
+    t_no_timers = true;
+    st = run(&I, 1, d_edges, capacity_edges, nullptr, nullptr, sp, KG_STATIC_SCRATCH_BYTES, stream, false,
+             nullptr, nullptr);
+    t_no_timers = false;
+    return st;
 }
 
 kg_status kg_gnp(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks, uint32_t *d_edges,

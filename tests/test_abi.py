@@ -158,6 +158,29 @@ def test_rgg_argument_checks_and_workspace(L):
     assert L.kg_rgg2d(2**32, 0.1, 1, None, None, 0, None, None, 0, None) == _lib.KG_ERANGE
 
 
+def test_static_scratch_entry_point_checks(L, kgref):
+    """kg_gnm_static takes kg_gnm's argument checks, and refuses an instance
+    whose workspace exceeds the static scratch (96 MiB) with KG_ESCRATCH,
+    all before it touches a device; the headline instance fits."""
+    import ctypes
+    from paper_1710_07565_amd import _lib
+    assert _lib.KG_STATIC_SCRATCH_BYTES == 96 << 20
+    assert L.kg_gnm_static(100, 10, 1, 1, 0, None, 10, None) == _lib.KG_EINVAL
+    assert L.kg_gnm_static(100, 10**6, 1, 1, 4, None, 10**6, None) == _lib.KG_EINVAL
+    assert L.kg_gnm_static(100, 10, 1, 1, 4, 8, 5, None) == _lib.KG_ENOSPC
+    assert L.kg_gnm_static(100, 10, 1, 1, 4, 4, 10, None) == _lib.KG_EINVAL      # misaligned output
+    b = ctypes.c_uint64()
+    big = _lib.KgInstance(2**27, 0, 0, 2**32, 0.0, 1, 4096, 0)
+    assert L.kg_workspace_bytes(ctypes.byref(big), 1, ctypes.byref(b)) == 0
+    assert b.value > _lib.KG_STATIC_SCRATCH_BYTES
+    # the output pointer is never used: the size check comes first
+    assert L.kg_gnm_static(2**27, 2**32, 0, 1, 4096, 4096, 2**32, None) == _lib.KG_ESCRATCH
+    assert b"static scratch" in L.kg_strerror(_lib.KG_ESCRATCH)
+    head = _lib.KgInstance(2**26, 0, 0, 2**31, 0.0, 1, 256, 0)
+    assert L.kg_workspace_bytes(ctypes.byref(head), 1, ctypes.byref(b)) == 0
+    assert b.value <= _lib.KG_STATIC_SCRATCH_BYTES
+
+
 def test_set_workspace_argument_checks(L):
     """kg_set_workspace refuses a NULL buffer with a size, a buffer without
     one and a pointer that is not 256-byte aligned, before asking for a
