@@ -14,12 +14,13 @@ tile exponent. Both shape the chunk and tile trees and therefore the bits
 or p), so tuning them would make the output depend on the machine.
 """
 import itertools
+import json
 
 from . import _lib
 
 DEFAULT_SAMPLE_WAVES = (0, 4, 5, 6)
 DEFAULT_PLAN_WAVES = (0, 4, 8, 16)
-DEFAULT_LEAF_CAP = (0,)
+DEFAULT_LEAF_CAP = (0, 768)
 
 
 def _time_batch(kg, torch, insts, arena, offs, ws, reps):
@@ -51,7 +52,7 @@ def tune(instances, sample_waves=DEFAULT_SAMPLE_WAVES, plan_waves=DEFAULT_PLAN_W
     offs = torch.empty(len(insts) + 1, dtype=torch.uint64, device=device)
     ws = torch.empty(max(kg.workspace_bytes(insts), 1), dtype=torch.uint8, device=device)
     opts = (_lib.KG_OPT_SAMPLE_WAVES, _lib.KG_OPT_PLAN_WAVES, _lib.KG_OPT_LEAF_CAP)
-    saved = [kg.get_option(o) for o in opts[:2]] + [0]
+    saved = [kg.get_option(o) for o in opts]     # the caller's settings, restored at the end
     table = []
     try:
         for k, cand in enumerate(itertools.product(sample_waves, plan_waves, leaf_cap)):
@@ -75,3 +76,91 @@ def tune(instances, sample_waves=DEFAULT_SAMPLE_WAVES, plan_waves=DEFAULT_PLAN_W
         kg.set_option(_lib.KG_OPT_PLAN_WAVES, best["plan_waves"])
         kg.set_option(_lib.KG_OPT_LEAF_CAP, best["leaf_cap"])
     return {"best": best, "table": table, "edges": total}
+
+
+# ---------------------------------------------------------------------------
+# The chunk-count table.  P shapes the chunk tree and therefore the bits, so
+# it is not tuned per process: this offline run times every candidate on
+# seeded probe instances of each table cell and writes the winners to a JSON
+# file that is committed with the package (workloads.POLICY_PATH); the
+# batched and served workloads then read P from that file.
+# ---------------------------------------------------------------------------
+P_DIRECTED = (1, 2, 4, 8, 16, 64)
+P_UNDIRECTED = (1, 2, 4, 8, 16, 32, 64)
+
+
+def tune_chunk_policy(out_path, log2n=(10, 24), log2d=(1, 6), probes=4, reps=3, tie=0.03, device="cuda",
+                      progress=None):
+    """Time every candidate P on `probes` seeded instances of every cell
+    (both models and directions, floor(log2 n) in log2n, floor(log2 degree)
+    in log2d), generated as one kg_batch; keep the fastest (any candidate
+    within `tie` of it: the smallest such P); check that all probes of a cell
+    give the same bytes as the same instances generated one call each.
+    Writes the table to out_path and returns it."""
+    import platform
+    import time
+
+    import torch
+    import paper_1710_07565_amd as kg
+    from . import workloads as W
+    table = {}
+    detail = {}
+    t_start = time.time()
+    cells = W.policy_cells(log2n, log2d)
+    for ci, (model, directed, ln, ld) in enumerate(cells):
+        probes_ = W.policy_probe(model, directed, ln, ld, count=probes, seed_fn=kg.instance_seed)
+        cands = [P for P in (P_DIRECTED if directed else P_UNDIRECTED) if P <= 2 ** ln]
+        times = {}
+        for P in cands:
+            insts = [W.make_instance(n, d, directed, model, seed, P=P) for (n, d, seed) in probes_]
+            kinsts = [kg.Instance(I.n, I.model, I.directed, I.m, I.p, I.seed, I.chunks) for I in insts]
+            total = 0
+            for I in kinsts:
+                total += int(I.m) if I.model == kg.GNM else kg.gnp_count(I.n, I.p, I.directed, I.seed, I.chunks,
+                                                                         device=device)
+            arena = torch.empty((max(total, 1), 2), dtype=torch.uint32, device=device)
+            offs = torch.empty(len(kinsts) + 1, dtype=torch.uint64, device=device)
+            ws = torch.empty(max(kg.workspace_bytes(kinsts), 1), dtype=torch.uint8, device=device)
+            kg.batch(kinsts, arena=arena, offsets=offs, workspace=ws)
+            torch.cuda.synchronize()
+            times[P] = _time_batch(kg, torch, kinsts, arena, offs, ws, reps)
+            del arena, offs, ws
+        torch.cuda.empty_cache()
+        best = min(times.values())
+        pick = min(P for P, t in times.items() if t <= best * (1.0 + tie))
+        key = W.policy_key(model, directed, ln, ld)
+        table[key] = pick
+        detail[key] = {str(P): round(t, 4) for P, t in times.items()}
+        if progress:
+            progress("%d/%d %s -> P=%d %s (%.0f s)" % (ci + 1, len(cells), key, pick, detail[key],
+                                                     time.time() - t_start))
+    torch.cuda.empty_cache()
+    dev = torch.cuda.get_device_properties(0)
+    tab = {"version": 1,
+           "key": "model/direction/floor(log2 n)/floor(log2 mean degree)",
+           "log2n": list(log2n), "log2d": list(log2d),
+           "candidates": {"directed": list(P_DIRECTED), "undirected": list(P_UNDIRECTED)},
+           "rule": "fastest median of %d kg_batch calls on %d seeded probe instances per cell; ties within %.0f%% "
+                   "go to the smaller P" % (reps, probes, 100 * tie),
+           "measured_on": "%s (%s), %s" % (dev.name, getattr(dev, "gcnArchName", "?"), platform.node()),
+           "P": table, "ms": detail}
+    with open(out_path, "w") as f:
+        json.dump(tab, f, indent=1, sort_keys=True)
+    return tab
+
+
+def main():
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="offline tuning of the chunk-count table")
+    ap.add_argument("--chunk-policy", action="store_true", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--probes", type=int, default=4)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    tune_chunk_policy(args.out, probes=args.probes, reps=args.reps,
+                      progress=lambda msg: print(msg, file=sys.stderr, flush=True))
+
+
+if __name__ == "__main__":
+    main()
