@@ -16,7 +16,7 @@
 namespace kg {
 
 constexpr uint32_t kFastDraws = 832;    // draws of one wave's base case (at most 4 Philox blocks per lane)
-constexpr uint32_t kKeyWords = 840;     // LDS key words: >= kFastDraws + 3 and >= the widest window span (838)
+constexpr uint32_t kKeyWords = 896;     // LDS key words: >= kFastDraws + 3 and >= the widest sort span (64 x 14)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // Wave-uniform 64-bit load through the scalar data cache.  Only for data
@@ -120,86 +120,15 @@ struct TileWalk {
     }
 };
 
-// Sorting and merging networks for the window passes (comparator pairs,
-// checked exhaustively by the 0-1 principle): an optimal 8-key sort,
-// Batcher's merge-exchange sorts of 10, 12 and 13 keys, and merges of two
-// sorted runs (4+4, 5+5, 6+6, 7+6 keys) obtained from those sorts by dropping
-// every comparator the merge does not need.
-__device__ __forceinline__ void cx(uint32_t *v, int a, int b)
+// Lane-to-lane moves of the sort (wave-wide DPP shifts by one lane); the
+// lane without a source keeps `edge`.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x, uint32_t edge)
 {
-    const uint32_t x = v[a], y = v[b];
-    v[a] = x < y ? x : y;
-    v[b] = x < y ? y : x;
+    return __builtin_amdgcn_update_dpp(edge, x, 0x130, 0xF, 0xF, false);   // wave_shl:1, lane 63 keeps edge
 }
-
-template <int W> __device__ __forceinline__ void net_sort(uint32_t *v);
-template <int W> __device__ __forceinline__ void net_merge(uint32_t *v);
-
-template <> __device__ __forceinline__ void net_sort<8>(uint32_t *v)
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x, uint32_t edge)
 {
-    constexpr uint8_t n[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
-                                  {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
-#pragma unroll
-    for (int c = 0; c < 19; ++c) cx(v, n[c][0], n[c][1]);
-}
-template <> __device__ __forceinline__ void net_merge<8>(uint32_t *v)
-{
-    constexpr uint8_t n[9][2] = {{0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
-#pragma unroll
-    for (int c = 0; c < 9; ++c) cx(v, n[c][0], n[c][1]);
-}
-template <> __device__ __forceinline__ void net_sort<10>(uint32_t *v)
-{
-    constexpr uint8_t n[31][2] = {{0, 8}, {1, 9}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {4, 8}, {5, 9}, {0, 2}, {1, 3},
-                                  {4, 6}, {5, 7}, {2, 8}, {3, 9}, {2, 4}, {3, 5}, {6, 8}, {7, 9}, {0, 1}, {2, 3},
-                                  {4, 5}, {6, 7}, {8, 9}, {1, 8}, {1, 4}, {3, 6}, {5, 8}, {1, 2}, {3, 4}, {5, 6},
-                                  {7, 8}};
-#pragma unroll
-    for (int c = 0; c < 31; ++c) cx(v, n[c][0], n[c][1]);
-}
-template <> __device__ __forceinline__ void net_merge<10>(uint32_t *v)
-{
-    constexpr uint8_t n[15][2] = {{0, 8}, {1, 9}, {1, 5}, {2, 6}, {3, 7}, {4, 8}, {0, 2}, {4, 6}, {3, 5}, {7, 9},
-                                  {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9}};
-#pragma unroll
-    for (int c = 0; c < 15; ++c) cx(v, n[c][0], n[c][1]);
-}
-
-template <> __device__ __forceinline__ void net_sort<12>(uint32_t *v)
-{
-    constexpr uint8_t n[41][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {4, 8}, {5, 9},
-                                  {6, 10}, {7, 11}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {8, 10}, {9, 11}, {2, 8},
-                                  {3, 9}, {2, 4}, {3, 5}, {6, 8}, {7, 9}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9},
-                                  {10, 11}, {1, 8}, {3, 10}, {1, 4}, {3, 6}, {5, 8}, {7, 10}, {1, 2}, {3, 4},
-                                  {5, 6}, {7, 8}, {9, 10}};
-#pragma unroll
-    for (int c = 0; c < 41; ++c) cx(v, n[c][0], n[c][1]);
-}
-template <> __device__ __forceinline__ void net_merge<12>(uint32_t *v)
-{
-    constexpr uint8_t n[19][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {2, 6}, {3, 7}, {4, 8}, {5, 9}, {0, 2}, {1, 3},
-                                  {4, 6}, {5, 7}, {8, 10}, {9, 11}, {1, 2}, {3, 4}, {5, 6}, {7, 8}, {9, 10}};
-#pragma unroll
-    for (int c = 0; c < 19; ++c) cx(v, n[c][0], n[c][1]);
-}
-template <> __device__ __forceinline__ void net_sort<13>(uint32_t *v)
-{
-    constexpr uint8_t n[48][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {4, 12}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
-                                  {8, 12}, {4, 8}, {5, 9}, {6, 10}, {7, 11}, {0, 2}, {1, 3}, {4, 6}, {5, 7},
-                                  {8, 10}, {9, 11}, {2, 8}, {3, 9}, {6, 12}, {2, 4}, {3, 5}, {6, 8}, {7, 9},
-                                  {10, 12}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9}, {10, 11}, {1, 8}, {3, 10},
-                                  {5, 12}, {1, 4}, {3, 6}, {5, 8}, {7, 10}, {9, 12}, {1, 2}, {3, 4}, {5, 6},
-                                  {7, 8}, {9, 10}, {11, 12}};
-#pragma unroll
-    for (int c = 0; c < 48; ++c) cx(v, n[c][0], n[c][1]);
-}
-template <> __device__ __forceinline__ void net_merge<13>(uint32_t *v)
-{
-    constexpr uint8_t n[21][2] = {{0, 8}, {1, 9}, {2, 10}, {3, 11}, {4, 12}, {3, 7}, {4, 8}, {5, 9}, {6, 10},
-                                  {1, 3}, {5, 7}, {9, 11}, {2, 4}, {6, 8}, {10, 12}, {0, 1}, {2, 3}, {4, 5},
-                                  {6, 7}, {8, 9}, {10, 11}};
-#pragma unroll
-    for (int c = 0; c < 21; ++c) cx(v, n[c][0], n[c][1]);
+    return __builtin_amdgcn_update_dpp(edge, x, 0x138, 0xF, 0xF, false);   // wave_shr:1, lane 0 keeps edge
 }
 
 template <int W>
@@ -225,64 +154,65 @@ __device__ __forceinline__ uint32_t lane_here()
     return r;
 }
 
-// Lane-to-lane moves of the merge step (wave-wide DPP shifts by one lane);
-// the lane without a source keeps `edge`.
-__device__ __forceinline__ uint32_t from_next_lane(uint32_t x, uint32_t edge)
+__device__ __forceinline__ void cx(uint32_t &a, uint32_t &b)
 {
-    return __builtin_amdgcn_update_dpp(edge, x, 0x130, 0xF, 0xF, false);   // wave_shl:1, lane 63 keeps edge
-}
-__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x, uint32_t edge)
-{
-    return __builtin_amdgcn_update_dpp(edge, x, 0x138, 0xF, 0xF, false);   // wave_shr:1, lane 0 keeps edge
+    const uint32_t x = a, y = b;
+    a = x < y ? x : y;
+    b = x < y ? y : x;
 }
 
-// One window pass over s[0..span), span = 64 W + W/2, positions V.. padded
-// with ~0 (no key equals ~0).  Lane L loads window [W L, +W) and sorts it;
-// the windows shifted by H = W/2 (this lane's last W - H keys and the next
-// lane's first H, both sorted) are merged in registers, the next lane's part
-// travelling there and back by DPP; the result is stored in place.  It is
-// sorted unless a bucket of more than H + 1 keys lies across a window
-// boundary; every adjacent pair of [0, span) is compared once for repeats,
-// and the pairs between merged windows (the only places where order can
-// break) for order.  Returns the mask of lanes that saw a pair out of order
-// and sets dups to the equal pairs among the first V positions.
+// Sort of s[0, 64 W) (W even) after the bucket placement: the keys are in
+// bucket order (bucket = top bits), arbitrary inside a bucket, and no bucket
+// holds more than R keys.  Lane L holds positions [W L, W L + W) in
+// registers and the wave runs R rounds of odd-even transposition sort:
+// even rounds compare-exchange the pairs (2j, 2j + 1), all inside a lane;
+// odd rounds the pairs (2j + 1, 2j + 2), the pair across two lanes by DPP
+// (each lane computes its own side from the old values).  A pair of keys
+// from two buckets is already in order and never exchanged, so every bucket
+// is sorted on its own, as a sequence of at most R elements, which R rounds
+// of odd-even transposition sort (Knuth, TAOCP vol. 3, 5.3.4) always sort.
+// Returns the number of equal adjacent pairs among the first V positions.
 template <int W>
-__device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &dups)
+__device__ __forceinline__ uint32_t oddeven(uint32_t *s, uint32_t V, uint32_t R)
 {
-    constexpr int H = W / 2, U = W - H;
     const uint32_t lane = lane_here();
     const uint32_t p0 = W * lane;
-    uint32_t v[W], m[W];
+    uint32_t v[W];
     wload<W>(s, p0, v);
-    net_sort<W>(v);
+    // rounds in pairs (an extra round leaves a sorted sequence sorted)
+    for (uint32_t r = 0; r < R; r += 2) {
 #pragma unroll
-    for (int i = 0; i < U; ++i) m[i] = v[H + i];
+        for (int i = 0; i < W; i += 2) cx(v[i], v[i + 1]);
+        const uint32_t nx = from_next_lane(v[0], kNone);     // lane 63: the padding bound
+        const uint32_t pv = from_prev_lane(v[W - 1], 0u);    // lane 0: no predecessor
 #pragma unroll
-    for (int i = 0; i < H; ++i) m[U + i] = from_next_lane(v[i], kNone);   // lane 63: the padding
-    net_merge<W>(m);
+        for (int i = 1; i + 1 < W; i += 2) cx(v[i], v[i + 1]);
+        v[W - 1] = v[W - 1] < nx ? v[W - 1] : nx;
+        v[0] = v[0] > pv ? v[0] : pv;
+    }
+    wstore<W>(s, p0, v);
     uint32_t eq = 0;
 #pragma unroll
-    for (int i = 0; i + 1 < W; ++i) eq += __popcll(__ballot(m[i] == m[i + 1]));
-    // this lane keeps the merged window's lower part; the upper part goes
-    // back to the next lane (lane 0 keeps its sorted head)
-#pragma unroll
-    for (int i = 0; i < U; ++i) v[H + i] = m[i];
-#pragma unroll
-    for (int i = 0; i < H; ++i) v[i] = from_prev_lane(m[U + i], v[i]);
-    wstore<W>(s, p0, v);
-    // between merged windows, and inside lane 0's head
-    uint64_t bad = __ballot(v[H - 1] > v[H]);
-    eq += __popcll(__ballot(v[H - 1] == v[H]));
-    uint32_t he = 0;
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i + 1 < H; ++i) he += v[i] == v[i + 1];
-    }
-    eq += __builtin_amdgcn_readfirstlane(he);
-    // pairs inside the padding [V, span) are all equal; the pair (V - 1, V) is not
-    constexpr uint32_t span = 64 * W + H;
-    dups = eq - (span - 1 - V);
-    return bad;
+    for (int i = 0; i + 1 < W; ++i) eq += __popcll(__ballot(v[i] == v[i + 1]));
+    const uint32_t nx = from_next_lane(v[0], ~v[W - 1]);       // lane 63: a value unequal to its last key
+    eq += __popcll(__ballot(v[W - 1] == nx));
+    // the pairs inside the padding [V, 64 W) are all equal; (V - 1, V) is not
+    constexpr uint32_t span = 64 * W;
+    return V < span ? eq - (span - 1 - V) : eq;
+}
+
+// Maximum over the 64 lanes (DPP row shifts, then row broadcasts; lane 63
+// ends with the maximum).
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v)
+{
+    uint32_t t;
+    t = __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xF, 0xF, false); v = v > t ? v : t;   // row_shr:1
+    t = __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xF, 0xF, false); v = v > t ? v : t;   // row_shr:2
+    t = __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xF, 0xF, false); v = v > t ? v : t;   // row_shr:4
+    t = __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xF, 0xF, false); v = v > t ? v : t;   // row_shr:8
+    t = __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false); v = v > t ? v : t;   // row_bcast:15
+    t = __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false); v = v > t ? v : t;   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Base case of the common tiles.  Pass 1 (one Philox block per lane and
@@ -291,15 +221,16 @@ __device__ __forceinline__ uint64_t windows(uint32_t *s, uint32_t V, uint32_t &d
 // 512 32-bit counters -- and keeps the draws in registers (rejected ones as
 // ~0), together with its rank among the draws of its bucket (the value
 // the LDS atomic returned).  An exclusive scan turns the counters into bucket
-// starts; pass 2 places each draw at its bucket start plus its rank; the
-// window passes (8 to 13 keys per lane) then sort inside buckets and count
-// repeats.  While fewer than ke distinct values are seen, J grows by the
-// shortfall (each draw adds at most one new value).  Leaves the sorted set in
-// s[0..ke) and returns true, or returns false once J would exceed lim (or
-// in the rare cases the queue kernel handles); the counters are zero again
-// whenever it returns.
+// starts; pass 2 places each draw at its bucket start plus its rank; as
+// many rounds of odd-even transposition as the fullest bucket has keys (8 to
+// 14 keys per lane) then sort inside buckets, and repeats are counted.
+// While fewer than ke distinct values are seen, J grows by the shortfall
+// (each draw adds at most one new value).  Leaves the sorted set in s[0..ke)
+// and returns true, or returns false once J would exceed lim (or in the rare
+// cases the queue kernel handles); the counters are zero again whenever it
+// returns.
 constexpr uint32_t kBucketWords = 512;   // one 32-bit counter per bucket
-constexpr uint32_t kWindowPasses = 64;   // bound on window passes per tile
+constexpr uint32_t kMaxRounds = 32;      // a fuller bucket sends the tile to the queue
 
 __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t *cnt, uint32_t ke, uint32_t lim)
 {
@@ -315,7 +246,8 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         const uint32_t nit = uni((J + 255) >> 8);
         // rounds whose 256 draws all lie below J: in a full tile with keys
         // below 2^31 every such draw is valid and needs no checks
-        const uint32_t nclean = (t.full && t.bits < 32) ? uni(J >> 8) : 0u;
+        const bool nclean_tile = t.full && t.bits < 32;
+        const uint32_t nclean = nclean_tile ? uni(J >> 8) : 0u;
         uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
         bool hit = false;
         // the draws stay in registers (x[4 e + q] = draw 256 e + 4 lane + q)
@@ -336,13 +268,23 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                 // only the lanes whose block holds draws below J compute it
                 const U4 w = t.st.block_uniform_key(blk);
                 uint32_t v[4] = {w.x & t.mask, w.y & t.mask, w.z & t.mask, w.w & t.mask};
+                if (nclean_tile) {
+                    // a full tile with keys below 2^31: only draws past J drop out
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    // a draw past J or rejected adds 0 and is kept as ~0
-                    const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
-                    hit |= ok & (v[q] == kNone);
-                    rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
-                    v[q] = ok ? v[q] : kNone;
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = 4 * blk + q < J;
+                        rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
+                        v[q] = ok ? v[q] : kNone;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // a draw past J or rejected adds 0 and is kept as ~0
+                        const bool ok = (4 * blk + q < J) & (t.full | (v[q] < S32));
+                        hit |= ok & (v[q] == kNone);
+                        rk[4 * e + q] = atomicAdd(&cnt[v[q] >> shift], ok ? 1u : 0u);
+                        v[q] = ok ? v[q] : kNone;
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) x[4 * e + q] = v[q];
@@ -356,12 +298,17 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
             return false;
         }
         uint32_t V;             // valid draws
+        uint32_t R;             // keys in the fullest bucket
         {
             const uint4 c0 = cw[0], c1 = cw[1];
             uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
             uint32_t sum = 0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) sum += w[i];
+            uint32_t mx = w[0];
+#pragma unroll
+            for (int i = 1; i < 8; ++i) mx = mx > w[i] ? mx : w[i];
+            R = wave_max32(mx);
             const uint32_t incl = wave_incl_scan32(sum);
             uint32_t run = incl - sum;
 #pragma unroll
@@ -393,7 +340,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t xv = x[4 * e + q];
                         // a ~0 entry lands in the padding after the V keys, which is
-                        // rewritten below (every window span exceeds V by at least 4)
+                        // rewritten below or lies past the sorted span (kKeyWords >= V + 4)
                         const uint32_t pos = xv != kNone ? old[q] : V + (lane & 3);
                         s[pos] = xv;
                     }
@@ -405,27 +352,19 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         cw[0] = make_uint4(0, 0, 0, 0);
         cw[1] = make_uint4(0, 0, 0, 0);
         __syncthreads();
-        uint32_t ndup = 0;
+        if (R > kMaxRounds) return false;
+        uint32_t ndup;
         {
-            // window width from V: 8, 10, 12 or 13 keys per lane
+            // keys per lane from V: 8, 10, 12 or 14; [V, 64 W) is padded with ~0
             const int mode = V <= 512 ? 0 : V <= 640 ? 1 : V <= 768 ? 2 : 3;
-            const uint32_t span = mode == 0 ? 516 : mode == 1 ? 645 : mode == 2 ? 774 : 838;
+            const uint32_t span = mode == 0 ? 512 : mode == 1 ? 640 : mode == 2 ? 768 : 896;
             for (uint32_t p = V + lane; p < span; p += 64) s[p] = kNone;
-            // one or two passes sort a tile in practice; one still unsorted
-            // after kWindowPasses passes goes to the queue (the general path
-            // gives the same bits), so the loop always ends
-            uint32_t pass = 0;
-            for (;; ++pass) {
-                if (pass == kWindowPasses) return false;
-                __syncthreads();
-                uint64_t bad;
-                if (mode == 0) bad = windows<8>(s, V, ndup);
-                else if (mode == 1) bad = windows<10>(s, V, ndup);
-                else if (mode == 2) bad = windows<12>(s, V, ndup);
-                else bad = windows<13>(s, V, ndup);
-                __syncthreads();
-                if (!bad) break;
-            }
+            __syncthreads();
+            if (mode == 0) ndup = oddeven<8>(s, V, R);
+            else if (mode == 1) ndup = oddeven<10>(s, V, R);
+            else if (mode == 2) ndup = oddeven<12>(s, V, R);
+            else ndup = oddeven<14>(s, V, R);
+            __syncthreads();
         }
         const uint32_t D = V - ndup;
         if (D == ke) {
@@ -479,9 +418,14 @@ __device__ __forceinline__ DecV dec_vregs(const Decoder &d)
 // Directed (TYPE 0) or rectangle (TYPE 1) slot with a 32-bit dividend:
 // quotient by shift or by the binary64 reciprocal estimate, corrected once
 // without branches.
-template <int TYPE, bool POW2>
+template <int TYPE, bool POW2, bool ALIGNED = false>
 __device__ __forceinline__ uint2 dec_narrow(const DecV &d, uint32_t x)
 {
+    if (ALIGNED) {
+        // rectangle, width 2^sh, tile starting at a row start, first column a
+        // multiple of the width: row offset by shift, column by mask and OR
+        return make_uint2(d.r0 + (x >> d.sh), d.b | (x & d.msk));
+    }
     const uint32_t y = d.c0 + x;
     uint32_t q, r;
     if (POW2) {
@@ -504,7 +448,7 @@ __device__ __forceinline__ uint2 dec_narrow(const DecV &d, uint32_t x)
 
 // Sorted keys s[0..n) out as edges o0 .. o0 + n - 1, four keys per lane per
 // round (lane-strided, so each store instruction covers 512 contiguous bytes).
-template <int TYPE, bool POW2>
+template <int TYPE, bool POW2, bool ALIGNED = false>
 __device__ __forceinline__ void emit_narrow(const TileCtx &t, const uint32_t *s, uint32_t n)
 {
     const DecV d = dec_vregs(t.dec);
@@ -519,7 +463,7 @@ __device__ __forceinline__ void emit_narrow(const TileCtx &t, const uint32_t *s,
 #pragma unroll
         for (int i = 0; i < 4; ++i) x[i] = s[b + lane + 64 * i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ol[64 * i] = dec_narrow<TYPE, POW2>(d, x[i]);
+        for (int i = 0; i < 4; ++i) ol[64 * i] = dec_narrow<TYPE, POW2, ALIGNED>(d, x[i]);
     }
     if (nfull < n) {
         uint32_t x[4];
@@ -531,7 +475,7 @@ __device__ __forceinline__ void emit_narrow(const TileCtx &t, const uint32_t *s,
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t p = nfull + lane + 64 * i;
-            if (p < n) out[p] = dec_narrow<TYPE, POW2>(d, x[i]);
+            if (p < n) out[p] = dec_narrow<TYPE, POW2, ALIGNED>(d, x[i]);
         }
     }
 }
@@ -543,7 +487,9 @@ __device__ __forceinline__ void emit_tile(const TileCtx &t, const uint32_t *s, u
     else if (d.type == 0) {
         if (d.pow2) emit_narrow<0, true>(t, s, n); else emit_narrow<0, false>(t, s, n);
     } else {
-        if (d.pow2) emit_narrow<1, true>(t, s, n); else emit_narrow<1, false>(t, s, n);
+        if (d.pow2 && d.c0 == 0 && (d.b & (d.dv - 1)) == 0) emit_narrow<1, true, true>(t, s, n);
+        else if (d.pow2) emit_narrow<1, true>(t, s, n);
+        else emit_narrow<1, false>(t, s, n);
     }
 }
 
