@@ -220,7 +220,8 @@ static double stirling_corr(double z)
     return r * (1.0 / 12.0 - r2 * (1.0 / 360.0 - r2 * (1.0 / 1260.0)));
 }
 
-/* ln((a+d)!) - ln(a!) for a >= 1024, d >= 1, a + d < 2^53.  With z = a+1:
+/* ln((a+d)!) - ln(a!) for a >= 1024, d >= 1, a + d < 2^64 (above 2^53 the
+ * conversions to binary64 round to nearest, even).  With z = a+1:
  * (z - 1/2) log1p(d/z) + d (log(z+d) - 1) + corr(z+d) - corr(z),
  * which never subtracts two large log-factorials. */
 static double stirling_diff(uint64_t a, uint64_t d)
@@ -234,7 +235,7 @@ static double stirling_diff(uint64_t a, uint64_t d)
     return (t1 + t2) + t3;
 }
 
-/* lnf(y) - lnf(x) for 0 <= x, y < 2^53. */
+/* lnf(y) - lnf(x) for 0 <= x, y < 2^64. */
 double kgref_lnf_diff(uint64_t x, uint64_t y)
 {
     lnf_init();
@@ -275,6 +276,8 @@ static uint64_t rou_sample(stream_t *s, double a, double h, uint64_t upper,
         double t = a + h * (V - 0.5) / U;
         if (!(t >= 0.0) || t >= upper_excl) continue;
         uint64_t X = (uint64_t)floor(t);
+        /* above 2^53, upper + 1 rounds in binary64: keep X in range exactly */
+        if (X > upper) continue;
         double T = lr(X, ctx);
         if (U * (4.0 - U) - 3.0 <= T) return X;     /* 2 log U <= 4U - U^2 - 3 */
         if (U * (U - T) >= 1.0) continue;            /* 2 log U >  U - 1/U      */
@@ -430,16 +433,31 @@ static uint64_t slots_total(const kgref_inst *I)
     return I->directed ? I->n * (I->n - 1) : I->n * (I->n - 1) / 2;
 }
 
+uint32_t kgref_tile_exponent(const kgref_inst *I);
+
 int kgref_validate(const kgref_inst *I)
 {
     if (I->n < 1 || I->P < 1 || (uint64_t)I->P > I->n) return KGREF_EINVAL;
     if (I->model > 1) return KGREF_EINVAL;
     if (I->n > (1ull << 32)) return KGREF_ERANGE;
     u128 N = I->directed ? (u128)I->n * (I->n - 1) : (u128)I->n * (I->n - 1) / 2;
-    if (N >= ((u128)1 << 53)) return KGREF_ERANGE;
     if (I->directed ? (I->P > (1u << 31)) : (I->P > (1u << 15))) return KGREF_ERANGE;
     if (I->model == 0 && I->m > (uint64_t)N) return KGREF_EINVAL;
     if (I->model == 1 && !(I->p >= 0.0 && I->p <= 1.0)) return KGREF_EINVAL;
+    if (N >= ((u128)1 << 53)) {
+        /* Universes of 2^53 slots and more (n <= 2^32, so N < 2^64): slot
+         * indices stay 64-bit integers; counts must stay below 2^53 (the
+         * variates convert them exactly), the slot counts that are converted
+         * round to nearest. */
+        if (I->model == 0 && I->m >= ((uint64_t)1 << 53)) return KGREF_ERANGE;
+        if (I->model == 1 && (double)N * I->p >= 0x1p52) return KGREF_ERANGE;
+    }
+    /* every chunk has fewer than 2^31 tiles (the tile index is a 32-bit
+     * stream word) */
+    uint64_t s = kgref_tile_exponent(I);
+    uint64_t rows = (I->n + I->P - 1) / I->P;               /* rows of the largest section */
+    u128 Nc = I->directed ? (u128)rows * (I->n - 1) : (u128)rows * rows;
+    if ((Nc >> s) >= ((u128)1 << 31)) return KGREF_ERANGE;
     return KGREF_OK;
 }
 
@@ -1282,4 +1300,174 @@ void kgref_rgg_cell_points(uint64_t n, double r, uint64_t seed, uint64_t z, uint
 {
     uint32_t L = kgref_rgg_level(n, r);
     for (uint64_t j = 0; j < k; j++) rgg_point(seed, L, z, j, &out[2 * j], &out[2 * j + 1]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Three-dimensional random geometric graphs (Sec. 2.1.2, Sec. 5 with  */
+/* d = 3): n points uniform in the unit cube, an edge between every     */
+/* two points closer than r.  Cells of side 2^-L >= max(r, n^-1/3), L   */
+/* at most 10, from an octant recursion: a node (level l, Morton index  */
+/* z) holding k points draws 2^3 - 1 = 7 Bin(., 1/2) variates (the      */
+/* paper's 2^d - 1 binomials per split, Sec. 5.1): the lower z half     */
+/* (slot 0); the lower y halves of the lower and the upper z half       */
+/* (slots 1, 2); the lower x halves of the four (z, y) quarters (slots  */
+/* 3..6, in Morton order); stream (j, z, 7 l + slot, TAG_RTREE3).       */
+/* Point j of cell z: ((cx + U) h, (cy + V) h, (cz + W) h), U, V, W the */
+/* 64-bit draws 3j, 3j + 1, 3j + 2 of (z, 0, TAG_RPTS3).  Vertex ids in */
+/* Morton order of the cells (x bit low, then y, then z), then the      */
+/* points of a cell; an edge iff ((dx^2 + dy^2) + dz^2) < r^2 in        */
+/* binary64, each operation rounded; each pair once as u < v, in        */
+/* ascending (u, v).                                                    */
+/* ------------------------------------------------------------------ */
+#define TAG_RTREE3 10
+#define TAG_RPTS3 11
+#define KGREF_RGG3_MAX_LEVEL 10
+
+uint32_t kgref_rgg3_level(uint64_t n, double r)
+{
+    uint32_t L = 0;
+    while (L < KGREF_RGG3_MAX_LEVEL && ldexp(r, (int)L + 1) <= 1.0 && ((uint64_t)1 << (3 * (L + 1))) <= n) L++;
+    return L;
+}
+
+/* the seven binomial draws of node (l, z) holding k points -> the eight
+ * octant counts in Morton order (index x + 2 y + 4 z of the octant) */
+static void rgg3_split(uint64_t seed, uint32_t l, uint64_t z, uint64_t k, uint64_t q[8])
+{
+    uint32_t a = (uint32_t)z, b = 7 * l;
+    uint64_t lz = kgref_bin(k, 0.5, seed, a, b + 0, TAG_RTREE3);          /* z = 0 half */
+    uint64_t y0 = kgref_bin(lz, 0.5, seed, a, b + 1, TAG_RTREE3);         /* z = 0, y = 0 */
+    uint64_t y1 = kgref_bin(k - lz, 0.5, seed, a, b + 2, TAG_RTREE3);     /* z = 1, y = 0 */
+    uint64_t quarter[4] = {y0, lz - y0, y1, k - lz - y1};                  /* (y, z) = 00, 10, 01, 11 */
+    for (int i = 0; i < 4; i++) {
+        uint64_t x0 = kgref_bin(quarter[i], 0.5, seed, a, b + 3 + (uint32_t)i, TAG_RTREE3);
+        q[2 * i] = x0;
+        q[2 * i + 1] = quarter[i] - x0;
+    }
+}
+
+static void rgg3_tree(uint64_t seed, uint32_t L, uint32_t l, uint64_t z, uint64_t k, uint64_t *cells)
+{
+    if (l == L) { cells[z] = k; return; }
+    uint64_t q[8];
+    rgg3_split(seed, l, z, k, q);
+    for (int i = 0; i < 8; i++) rgg3_tree(seed, L, l + 1, 8 * z + (uint64_t)i, q[i], cells);
+}
+
+/* Point counts of all 8^L cells, Morton order. */
+int kgref_rgg3_cells(uint64_t n, double r, uint64_t seed, uint64_t *cells)
+{
+    uint32_t L = kgref_rgg3_level(n, r);
+    rgg3_tree(seed, L, 0, 0, n, cells);
+    return (int)L;
+}
+
+/* One cell's count from its root path only (no other node is drawn). */
+uint64_t kgref_rgg3_cell_count_path(uint64_t n, double r, uint64_t seed, uint64_t cell)
+{
+    uint32_t L = kgref_rgg3_level(n, r);
+    uint64_t k = n, z = 0;
+    for (uint32_t l = 0; l < L; l++) {
+        uint64_t q[8];
+        rgg3_split(seed, l, z, k, q);
+        uint64_t d = (cell >> (3 * (L - 1 - l))) & 7;
+        z = 8 * z + d;
+        k = q[d];
+    }
+    return k;
+}
+
+static void rgg3_cell_xyz(uint64_t z, uint32_t L, uint64_t c[3])
+{
+    c[0] = c[1] = c[2] = 0;
+    for (uint32_t i = 0; i < L; i++)
+        for (int d = 0; d < 3; d++) c[d] |= ((z >> (3 * i + (uint32_t)d)) & 1) << i;
+}
+
+static uint64_t rgg3_morton(const int64_t c[3], uint32_t L)
+{
+    uint64_t z = 0;
+    for (uint32_t i = 0; i < L; i++)
+        for (int d = 0; d < 3; d++) z |= (((uint64_t)c[d] >> i) & 1) << (3 * i + (uint32_t)d);
+    return z;
+}
+
+/* Point j of cell z. */
+static void rgg3_point(uint64_t seed, uint32_t L, uint64_t z, uint64_t j, double *out)
+{
+    stream_t s;
+    stream_init(&s, seed, (uint32_t)z, 0, TAG_RPTS3);
+    uint64_t c[3];
+    rgg3_cell_xyz(z, L, c);
+    double h = ldexp(1.0, -(int)L);
+    for (int d = 0; d < 3; d++) {
+        uint64_t t = 3 * j + (uint64_t)d;      /* 64-bit draw t: half t % 2 of block t / 2 */
+        uint32_t w[4];
+        stream_block(&s, t / 2, w);
+        uint64_t x = (t & 1) ? (((uint64_t)w[3] << 32) | w[2]) : (((uint64_t)w[1] << 32) | w[0]);
+        out[d] = ((double)c[d] + u64_to_unit(x)) * h;
+    }
+}
+
+static int rgg3_adjacent(const double *a, const double *b, double r2)
+{
+    double dx = a[0] - b[0];
+    double dy = a[1] - b[1];
+    double dz = a[2] - b[2];
+    return (dx * dx + dy * dy) + dz * dz < r2;
+}
+
+/* The whole graph: points (3n doubles, vertex order) and the edges in
+ * ascending (u, v), at most cap of them written.  Returns the edge count
+ * (which may exceed cap: then only the first cap are written), or a
+ * negative status. */
+int64_t kgref_rgg3d(uint64_t n, double r, uint64_t seed, double *pts, uint32_t *edges, uint64_t cap)
+{
+    if (!(r >= 0.0) || n > 0xFFFFFFFFull) return KGREF_EINVAL;
+    uint32_t L = kgref_rgg3_level(n, r);
+    uint64_t G = (uint64_t)1 << L, C = G * G * G;
+    uint64_t *cells = (uint64_t *)calloc(C, sizeof(uint64_t));
+    uint64_t *off = (uint64_t *)malloc((C + 1) * sizeof(uint64_t));
+    double *P = pts ? pts : (double *)malloc((3 * n + 3) * sizeof(double));
+    rgg3_tree(seed, L, 0, 0, n, cells);
+    off[0] = 0;
+    for (uint64_t z = 0; z < C; z++) off[z + 1] = off[z] + cells[z];
+    for (uint64_t z = 0; z < C; z++)
+        for (uint64_t j = 0; j < cells[z]; j++) rgg3_point(seed, L, z, j, &P[3 * (off[z] + j)]);
+    const double r2 = r * r;
+    uint64_t E = 0;
+    for (uint64_t z = 0; z < C; z++) {
+        uint64_t c[3], nb[27];
+        int nn = 0;
+        rgg3_cell_xyz(z, L, c);
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int64_t w[3] = {(int64_t)c[0] + dx, (int64_t)c[1] + dy, (int64_t)c[2] + dz};
+                    if (w[0] < 0 || w[1] < 0 || w[2] < 0 || w[0] >= (int64_t)G || w[1] >= (int64_t)G ||
+                        w[2] >= (int64_t)G)
+                        continue;
+                    uint64_t zz = rgg3_morton(w, L);
+                    if (zz >= z) nb[nn++] = zz;
+                }
+        qsort(nb, (size_t)nn, sizeof(uint64_t), cmp_u64r);
+        for (uint64_t a = off[z]; a < off[z + 1]; a++)
+            for (int i = 0; i < nn; i++)
+                for (uint64_t b = off[nb[i]]; b < off[nb[i] + 1]; b++) {
+                    if (b <= a || !rgg3_adjacent(&P[3 * a], &P[3 * b], r2)) continue;
+                    if (edges && E < cap) { edges[2 * E] = (uint32_t)a; edges[2 * E + 1] = (uint32_t)b; }
+                    E++;
+                }
+    }
+    free(cells);
+    free(off);
+    if (!pts) free(P);
+    return (int64_t)E;
+}
+
+/* The k points of cell z (3k doubles), as the whole generator makes them. */
+void kgref_rgg3_cell_points(uint64_t n, double r, uint64_t seed, uint64_t z, uint64_t k, double *out)
+{
+    uint32_t L = kgref_rgg3_level(n, r);
+    for (uint64_t j = 0; j < k; j++) rgg3_point(seed, L, z, j, &out[3 * j]);
 }

@@ -19,6 +19,7 @@ GNM, GNP = 0, 1
 TAG_DTREE, TAG_UTREE, TAG_CBIN, TAG_TTREE, TAG_TLEAF, TAG_INST = 1, 2, 3, 4, 5, 6
 TAG_RTREE, TAG_RPTS = 8, 9
 RGG_MAX_LEVEL = 14
+RGG3_MAX_LEVEL = 10
 
 
 def build(force=False):
@@ -82,6 +83,12 @@ def lib():
         L.kgref_rgg_cell_count_path.restype = u64
         L.kgref_rgg2d.argtypes = [u64, dbl, u64, vp, vp, u64]; L.kgref_rgg2d.restype = ctypes.c_int64
         L.kgref_rgg_cell_points.argtypes = [u64, dbl, u64, u64, u64, vp]; L.kgref_rgg_cell_points.restype = None
+        L.kgref_rgg3_level.argtypes = [u64, dbl]; L.kgref_rgg3_level.restype = u32
+        L.kgref_rgg3_cells.argtypes = [u64, dbl, u64, vp]; L.kgref_rgg3_cells.restype = ctypes.c_int
+        L.kgref_rgg3_cell_count_path.argtypes = [u64, dbl, u64, u64]
+        L.kgref_rgg3_cell_count_path.restype = u64
+        L.kgref_rgg3d.argtypes = [u64, dbl, u64, vp, vp, u64]; L.kgref_rgg3d.restype = ctypes.c_int64
+        L.kgref_rgg3_cell_points.argtypes = [u64, dbl, u64, u64, u64, vp]; L.kgref_rgg3_cell_points.restype = None
         _lib = L
     return _lib
 
@@ -312,5 +319,43 @@ def rgg2d(n, r, seed):
         raise ValueError("kgref_rgg2d status %d" % E)
     out = np.zeros((max(E, 1), 2), dtype=np.uint32)
     E2 = lib().kgref_rgg2d(int(n), float(r), seed, _ptr(pts), _ptr(out), E)
+    assert E2 == E
+    return pts[:int(n)], out[:E]
+
+
+def rgg3_level(n, r):
+    """Level L of the 8^L-cell grid of a three-dimensional RGG (Sec. 5, d = 3)."""
+    return int(lib().kgref_rgg3_level(int(n), float(r)))
+
+
+def rgg3_cells(n, r, seed):
+    """Point counts of all 8^L cells, Morton order (the octant recursion)."""
+    L = rgg3_level(n, r)
+    out = np.zeros(max(1, 8 ** L), dtype=np.uint64)
+    lib().kgref_rgg3_cells(int(n), float(r), int(seed) & (2**64 - 1), _ptr(out))
+    return out
+
+
+def rgg3_cell_count_path(n, r, seed, cell):
+    """One cell's count from its root path only (Sec. 5.1)."""
+    return int(lib().kgref_rgg3_cell_count_path(int(n), float(r), int(seed) & (2**64 - 1), int(cell)))
+
+
+def rgg3_cell_points(n, r, seed, cell, k):
+    """The k points (k, 3) of one cell."""
+    out = np.zeros((max(int(k), 1), 3), dtype=np.float64)
+    lib().kgref_rgg3_cell_points(int(n), float(r), int(seed) & (2**64 - 1), int(cell), int(k), _ptr(out))
+    return out[:int(k)]
+
+
+def rgg3d(n, r, seed):
+    """(points (n, 3) float64 in vertex order, edges (E, 2) uint32 ascending)."""
+    seed = int(seed) & (2**64 - 1)
+    pts = np.zeros((max(int(n), 1), 3), dtype=np.float64)
+    E = lib().kgref_rgg3d(int(n), float(r), seed, _ptr(pts), None, 0)
+    if E < 0:
+        raise ValueError("kgref_rgg3d status %d" % E)
+    out = np.zeros((max(E, 1), 2), dtype=np.uint32)
+    E2 = lib().kgref_rgg3d(int(n), float(r), seed, _ptr(pts), _ptr(out), E)
     assert E2 == E
     return pts[:int(n)], out[:E]
