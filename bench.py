@@ -571,36 +571,43 @@ def run_skip(args):
     return res
 
 
-def run_rgg(args):
-    """Two-dimensional random geometric graph (Sec. 5): n = 2^26 points,
-    r = 0.55 sqrt(ln n / n) (the radius of the paper's RGG experiments),
-    seeds 1..3; points and edges written to HBM every step."""
+def kg_rgg_level(n, r, dim):
+    """Level of the cell grid (the library's rule), for the workload name."""
+    L, lmax = 0, 14 if dim == 2 else 10
+    while L < lmax and r * 2.0 ** (L + 1) <= 1.0 and 2 ** (dim * (L + 1)) <= n:
+        L += 1
+    return L
+
+
+def run_rgg(args, dim=2):
+    """Random geometric graph (Sec. 5) in two or three dimensions: n = 2^26
+    points, r = 0.55 (ln n / n)^(1/dim) (the radius of the paper's RGG
+    experiments), seeds 1..3; points and edges written to HBM every step."""
     import torch
     import paper_1710_07565_amd as kg
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     n = 2**26
-    r = 0.55 * math.sqrt(math.log(n) / n)
+    r = 0.55 * (math.log(n) / n) ** (1.0 / dim)
+    gen = kg.rgg2d if dim == 2 else kg.rgg3d
+    wsb = kg.rgg2d_workspace_bytes if dim == 2 else kg.rgg3d_workspace_bytes
     seeds = [1, 2, 3]
-    ws = torch.empty(kg.rgg2d_workspace_bytes(n, r), dtype=torch.uint8, device=dev)
-    pts = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    ws = torch.empty(wsb(n, r), dtype=torch.uint8, device=dev)
+    pts = torch.empty((n, dim), dtype=torch.float64, device=dev)
     tot = torch.zeros(1, dtype=torch.uint64, device=dev)
     E = []
     for sd in seeds:
-        kg.rgg2d(n, r, sd, points=pts, out=torch.empty((0, 2), dtype=torch.uint32, device=dev), total=tot,
-                 workspace=ws)
+        gen(n, r, sd, points=pts, out=torch.empty((0, 2), dtype=torch.uint32, device=dev), total=tot,
+            workspace=ws)
         E.append(int(tot.view(torch.int64).cpu()[0]))
     out = torch.empty((max(E), 2), dtype=torch.uint32, device=dev)
 
     def step(i):
-        kg.rgg2d(n, r, seeds[i % 3], points=pts, out=out, total=tot, workspace=ws)
+        gen(n, r, seeds[i % 3], points=pts, out=out, total=tot, workspace=ws)
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
-    for k in range(5):
-        kg.kernel_time_read(k)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for i in range(args.steps):
@@ -608,6 +615,13 @@ def run_rgg(args):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # the per-kernel split in a separate pass (HIP events around every launch)
+    kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 1)
+    for k in range(5):
+        kg.kernel_time_read(k)
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
     per = {}
     for k, name in enumerate(["tree", "scans", "edge_count_pass", "edge_write_pass", "points"]):
         t, c = kg.kernel_time_read(k)
@@ -615,21 +629,23 @@ def run_rgg(args):
     kg.set_option(kg._lib.KG_OPT_TIME_KERNELS, 0)
     Etot = sum(E[i % 3] for i in range(args.steps))
     value = Etot / (ms * 1e-3)
-    bytes_step = [BYTES_PER_EDGE * E[i % 3] + 16 * n for i in range(args.steps)]
+    bytes_step = [BYTES_PER_EDGE * E[i % 3] + 8 * dim * n for i in range(args.steps)]
     wr_ms = per["edge_write_pass"]
     wr_bytes = BYTES_PER_EDGE * Etot / args.steps
+    cells = ("4^%d" % kg_rgg_level(n, r, dim)) if dim == 2 else ("8^%d" % kg_rgg_level(n, r, dim))
     res = {
         "metric": "edges/sec and % HBM write BW, 1 GPU; batched vs plain; p50/p99 latency served",
         "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+u32", "data": "synthetic",
-        "config": {"workload": "2D random geometric graph n=2^26 r=0.55 sqrt(ln n/n) (4^11 cells)",
+        "config": {"workload": "%dD random geometric graph n=2^26 r=0.55 (ln n/n)^(1/%d) (%s cells)" % (dim, dim, cells),
                    "n": n, "r": r, "seeds": seeds, "edges_per_step": E[0]},
         "pct_hbm_write_bw": 100.0 * sum(bytes_step) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "per_launch_ms": per,
         "roofline": {"bound": "hbm",
                      "limited_by": "per-vertex distance tests (FP64, neighbour points from L2), two passes",
-                     "kernel": "rgg_edges_kernel<true>", "avg_launch_ms": wr_ms,
+                     "kernel": "rgg_edges_kernel<true>" if dim == 2 else "rgg3_edges_kernel<true>",
+                     "avg_launch_ms": wr_ms,
                      "achieved": wr_bytes / (wr_ms * 1e-3) / 1e9, "unit": "GB/s", "peak": HBM_PEAK_GBS,
                      "frac": wr_bytes / (wr_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
     }
@@ -639,13 +655,14 @@ def run_rgg(args):
         # a bounded sample: the whole oracle on a 2^22-point instance of the
         # same recipe (one thread)
         ns = 2**22
-        rs = 0.55 * math.sqrt(math.log(ns) / ns)
+        rs = 0.55 * (math.log(ns) / ns) ** (1.0 / dim)
         t0 = _t.perf_counter()
-        _, Es = kgref.rgg2d(ns, rs, 1)
+        _, Es = (kgref.rgg2d if dim == 2 else kgref.rgg3d)(ns, rs, 1)
         dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": len(Es) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
-                               "sample": "n=2^22, r=0.55 sqrt(ln n/n), seed 1: %d edges in %.1f s, one thread"
-                               % (len(Es), dt)}
+        res["cpu_baseline"] = {"value": len(Es) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": "n=2^22, r=0.55 (ln n/n)^(1/%d), seed 1: %d edges in %.1f s, one thread"
+                               % (dim, len(Es), dt)}
     else:
         res["cpu_baseline"] = None
     return res
@@ -743,7 +760,7 @@ def main():
     ap.add_argument("--workload", default="gnm_undirected_n26_m31", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "views", "skip", "rgg"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "views", "skip", "rgg", "rgg3"])
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--arena-gib", type=float, default=96.0)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -802,8 +819,8 @@ def main():
     if args.mode == "skip":
         print(json.dumps(run_skip(args)), flush=True)
         return
-    if args.mode == "rgg":
-        print(json.dumps(run_rgg(args)), flush=True)
+    if args.mode in ("rgg", "rgg3"):
+        print(json.dumps(run_rgg(args, 2 if args.mode == "rgg" else 3)), flush=True)
         return
     desc = WORKLOADS[args.workload]
     res = run_plain(args, desc)

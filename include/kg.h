@@ -18,10 +18,15 @@
  *     undirected output always has u < v.
  *   - The bytes are a pure function of (n, m or p, directed, seed, P): they do
  *     not depend on the stream, the launch shape, tuning knobs or the device.
- *   - Limits: n <= 2^32, slot count N = n(n-1) (directed) or n(n-1)/2
- *     (undirected) below 2^53, 1 <= P <= n, P <= 2^31 directed, P <= 2^15
- *     undirected; at most 2^36 chunks in one call (a batch counts the
- *     chunks of all its instances).
+ *   - Limits: n <= 2^32 (so the slot count N = n(n-1) directed or
+ *     n(n-1)/2 undirected is below 2^64), 1 <= P <= n, P <= 2^31 directed,
+ *     P <= 2^15 undirected; fewer than 2^31 tiles in every chunk; at most
+ *     2^36 chunks in one call (a batch counts the chunks of all its
+ *     instances).  For N >= 2^53 (Sec. 1: universes beyond binary64's exact
+ *     integers) the edge count must stay below 2^53 (G(n,m): m < 2^53;
+ *     G(n,p): N p < 2^52); slot counts are then converted to binary64 by
+ *     rounding to nearest, identically in every implementation of the
+ *     bits.
  *   - Every device pointer is owned by the caller; the library never frees
  *     caller memory.  `stream` is a hipStream_t (NULL = default stream).
  *     Calls are asynchronous on `stream` unless stated otherwise; argument
@@ -200,6 +205,35 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
                    uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
                    void *stream);
 
+/* Three-dimensional random geometric graph (Sec. 2.1.2 model with d = 3,
+ * Sec. 5 generator): n points uniform in [0,1)^3 and an edge between every
+ * two points at distance below r.  The cube is cut into 8^L cells of side
+ * 2^-L, L the largest level <= 10 with 2^L r <= 1 and 8^L <= n; the points
+ * per cell come from an octant recursion of seven Bin(k, 1/2) variates per
+ * node (the 2^d - 1 binomials of Sec. 5.1; Philox counter (j, Morton index,
+ * 7 level + slot, 10): slot 0 the lower z half, 1 and 2 the lower y halves
+ * of the lower and upper z half, 3..6 the lower x halves of the four (y, z)
+ * quarters); point j of a cell takes the 64-bit draws 3j, 3j + 1, 3j + 2 of
+ * counter (., cell, 0, 11) for x, y, z; the edges come from a count pass,
+ * a scan and a write pass over each point's cell and its 26 neighbours
+ * (Sec. 5.3).  The output does not depend on any launch setting.
+ *   d_points  device, n x (double x, double y, double z), 8-byte aligned,
+ *             in vertex order: cells in Morton order (x bit lowest, then y,
+ *             then z), then the cell's points.  May be NULL only if n == 0.
+ *   d_edges   device, capacity_edges x (uint32 u, uint32 v), u < v, in
+ *             ascending (u, v); ((x_u - x_v)^2 + (y_u - y_v)^2) +
+ *             (z_u - z_v)^2 < r^2 in binary64 with every operation rounded.
+ *             Nothing is written if the total exceeds capacity_edges.
+ *   d_total   device uint64, may be NULL: the edge total.
+ * n < 2^32, r >= 0 (KG_EINVAL for NaN or negative r); KG_ERANGE if
+ * n^2 / 8^L > 2^36.  Asynchronous on `stream`; the workspace (or, if
+ * d_workspace is NULL, a stream-ordered allocation) holds
+ * kg_rgg3d_workspace_bytes. */
+kg_status kg_rgg3d_workspace_bytes(uint64_t n, double r, uint64_t *bytes);
+kg_status kg_rgg3d(uint64_t n, double r, uint64_t seed, double *d_points, uint32_t *d_edges,
+                   uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
+                   void *stream);
+
 /* kg_batch in two parts, so that the generating part can be recorded into a
  * HIP graph (stream capture) and replayed.  kg_batch_upload writes the
  * descriptor table of the list into d_workspace (required, at least
@@ -213,7 +247,7 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
  * already have been used once on the device (any call), and only these calls
  * are accepted, each with a caller workspace (passed, or registered with
  * kg_set_workspace): kg_batch_launch, kg_gnm, kg_gnp, kg_pe_view,
- * kg_chunk_counts, kg_gnp_skip, kg_rgg2d and kg_eval; the others return
+ * kg_chunk_counts, kg_gnp_skip, kg_rgg2d, kg_rgg3d and kg_eval; the others return
  * KG_EINVAL before enqueuing anything.  A replayed graph rewrites the same
  * bytes; replays that overlap in time must not share the arena or the
  * workspace. */

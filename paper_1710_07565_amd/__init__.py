@@ -354,6 +354,64 @@ def rgg2d(n, r, seed=1, points=None, out=None, total=None, workspace=None, strea
     return points, edges[:E]
 
 
+def rgg3d_workspace_bytes(n, r):
+    b = ctypes.c_uint64(0)
+    _lib.check(_lib.lib().kg_rgg3d_workspace_bytes(int(n), float(r), ctypes.byref(b)), "kg_rgg3d_workspace_bytes")
+    return int(b.value)
+
+
+def rgg3d_expected_edges(n, r):
+    """Mean edge count of the three-dimensional RGG: C(n, 2) times the chance
+    that two uniform points of the unit cube lie closer than r (for r <= 1:
+    4 pi r^3 / 3 - 3 pi r^4 / 2 + 8 r^5 / 5 - r^6 / 6)."""
+    import math
+    pairs = n * (n - 1) / 2.0
+    if r <= 1.0:
+        return pairs * (4.0 * math.pi * r ** 3 / 3.0 - 1.5 * math.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6.0)
+    return pairs
+
+
+def rgg3d(n, r, seed=1, points=None, out=None, total=None, workspace=None, stream=None, device="cuda"):
+    """Three-dimensional random geometric graph (kg_rgg3d).  Returns
+    (points (n, 3) float64, edges (E, 2) uint32).  With `out` given, writes
+    into it and returns (points, out, total) without synchronising; if the
+    total exceeds out.shape[0] nothing is written to `out`."""
+    torch = _torch()
+    dev = out.device if out is not None else (points.device if points is not None else torch.device(device))
+    with _on(stream):
+        if points is None:
+            points = torch.empty((int(n), 3), dtype=torch.float64, device=dev)
+        if workspace is None:
+            workspace = torch.empty(max(rgg3d_workspace_bytes(n, r), 1), dtype=torch.uint8, device=dev)
+        if total is None:
+            total = torch.zeros(1, dtype=torch.uint64, device=dev)
+
+    def call(edges):
+        st = _lib.lib().kg_rgg3d(int(n), float(r), int(seed) & (2**64 - 1),
+                                 points.data_ptr() if points.numel() else None,
+                                 edges.data_ptr() if edges.numel() else None, edges.shape[0], total.data_ptr(),
+                                 workspace.data_ptr(), workspace.numel(), _stream(stream))
+        _lib.check(st, "kg_rgg3d")
+
+    if out is not None:
+        call(out)
+        return points, out, total
+    import math
+    mu = rgg3d_expected_edges(int(n), float(r))
+    cap = int(min(n * (n - 1) // 2, mu * 1.05 + 8.0 * math.sqrt(mu + 1.0) * max(1.0, (n * r ** 3 * 30.0) ** 0.5)
+                  + 1024))
+    with _on(stream):
+        edges = torch.empty((max(cap, 0), 2), dtype=torch.uint32, device=dev)
+    call(edges)
+    _sync(stream, dev)
+    E = int(total.view(torch.int64).cpu()[0])
+    if E > edges.shape[0]:
+        with _on(stream):
+            edges = torch.empty((E, 2), dtype=torch.uint32, device=dev)
+        call(edges)
+    return points, edges[:E]
+
+
 def batch_upload(instances, workspace, stream=None):
     """Write the descriptor table of `instances` into `workspace` (a device
     uint8 tensor of at least workspace_bytes(instances)); synchronises."""

@@ -13,7 +13,7 @@ KG_OPT_LEAF_CAP, KG_OPT_SAMPLE_WAVES, KG_OPT_PLAN_WAVES = 1, 2, 3
 
 EXPORTS = ["kg_spec_version", "kg_strerror", "kg_workspace_bytes", "kg_set_workspace", "kg_gnm", "kg_gnp", "kg_gnp_count",
            "kg_chunk_counts", "kg_batch", "kg_batch_upload", "kg_batch_launch", "kg_pe_view", "kg_gnp_skip",
-           "kg_rgg2d_workspace_bytes", "kg_rgg2d", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_eval",
+           "kg_rgg2d_workspace_bytes", "kg_rgg2d", "kg_rgg3d_workspace_bytes", "kg_rgg3d", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_eval",
            "kg_kernel_time_read", "kg_edge_hash", "kg_gnm_static"]
 KG_OPT_TIME_KERNELS = 4
 KG_KERNEL_COUNT, KG_KERNEL_SCAN, KG_KERNEL_PLAN, KG_KERNEL_SAMPLE, KG_KERNEL_QUEUE = 0, 1, 2, 3, 4
@@ -64,6 +64,8 @@ def lib():
     L.kg_gnp_skip.restype = i32
     L.kg_rgg2d_workspace_bytes.argtypes = [u64, dbl, vp]; L.kg_rgg2d_workspace_bytes.restype = i32
     L.kg_rgg2d.argtypes = [u64, dbl, u64, vp, vp, u64, vp, vp, u64, vp]; L.kg_rgg2d.restype = i32
+    L.kg_rgg3d_workspace_bytes.argtypes = [u64, dbl, vp]; L.kg_rgg3d_workspace_bytes.restype = i32
+    L.kg_rgg3d.argtypes = [u64, dbl, u64, vp, vp, u64, vp, vp, u64, vp]; L.kg_rgg3d.restype = i32
     L.kg_batch_launch.argtypes = [ip, u32, vp, u64, vp, vp, u64, vp]; L.kg_batch_launch.restype = i32
     L.kg_instance_seed.argtypes = [u64, u32]; L.kg_instance_seed.restype = u64
     L.kg_set_option.argtypes = [ctypes.c_int, ctypes.c_int64]; L.kg_set_option.restype = i32

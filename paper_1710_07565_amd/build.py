@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkg.so")
 SOURCES = [os.path.join(HERE, "csrc", "kg_lib.hip")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kg_device.hpp", "kg_kernels.hpp", "kg_tile.hpp", "kg_skip.hpp",
-                                                                   "kg_rgg.hpp", "kg_hash.hpp")] + \
+                                                                   "kg_rgg.hpp", "kg_rgg3.hpp", "kg_hash.hpp")] + \
     [os.path.join(ROOT, "include", "kg.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KG_OFFLOAD_ARCH", "gfx950")

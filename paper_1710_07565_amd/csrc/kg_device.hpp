@@ -305,6 +305,7 @@ __device__ __forceinline__ uint64_t rou_sample(const Stream &s, double a, double
         const double t = a + h * (V - 0.5) / U;
         if (!(t >= 0.0) || t >= upper_excl) continue;
         const uint64_t X = (uint64_t)floor(t);
+        if (X > upper) continue;        // upper + 1 rounds in binary64 above 2^53
         const double T = ratio(X);
         if (U * (4.0 - U) - 3.0 <= T) return X;
         if (U * (U - T) >= 1.0) continue;
@@ -403,6 +404,7 @@ struct HypRun {
         const double t = a + h * (V - 0.5) / U;
         if (!(t >= 0.0) || t >= upper_excl) return false;
         const uint64_t X = (uint64_t)floor(t);
+        if (X > lo) return false;
         const double T = HypRatio{N, hi, lo, M}(X);
         bool acc = false;
         if (U * (4.0 - U) - 3.0 <= T) acc = true;

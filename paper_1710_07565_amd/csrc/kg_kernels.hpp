@@ -382,8 +382,8 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
 // Directed: slot w of row u (w in [0, n-1)) is column w + [w >= u].
 // Rectangle: local l -> (row r0 + l / width, column b + l % width).
 // Triangle: rows counted from the bottom hold 1, 2, 3, ... slots.
-// Because N < 2^53, n < 2^27: rows, columns, section sizes and the divisor
-// fit 32 bits.  The dividend c0 + x fits 32 bits unless the tile has close
+// Because n <= 2^32, rows, columns, section sizes and the divisor fit 32
+// bits.  The dividend c0 + x fits 32 bits unless the tile has close
 // to 2^32 slots ("wide").  Divisions use a binary64 reciprocal estimate
 // corrected by one step (exact for dividends below 2^33), or a shift when
 // the divisor is a power of two.
@@ -432,7 +432,8 @@ struct Decoder {
         const uint64_t l = lbase + x;
         const uint64_t lr = Ttri - 1 - l;
         // largest q with q(q+1)/2 <= lr: the binary64 estimate is within one
-        // of it for lr < 2^53, so each correction runs at most twice
+        // of it (lr < 2^63: the rounding of lr moves the square root by far
+        // less than one), so each correction runs at most twice
         uint64_t q = (uint64_t)((sqrt(8.0 * (double)lr + 1.0) - 1.0) * 0.5);
         for (int i = 0; i < 2 && q * (q + 1) / 2 > lr; ++i) --q;
         for (int i = 0; i < 2 && (q + 1) * (q + 2) / 2 <= lr; ++i) ++q;

@@ -15,6 +15,7 @@
 #include "kg_tile.hpp"
 #include "kg_skip.hpp"
 #include "kg_rgg.hpp"
+#include "kg_rgg3.hpp"
 #include "kg_hash.hpp"
 
 namespace kg {
@@ -160,11 +161,16 @@ kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
     if (in.flags > in.chunks) return KG_EINVAL;     // 0, or 1 + the section of a view
     if (in.n > (1ull << 32)) return KG_ERANGE;
     const u128 N128 = in.directed ? (u128)in.n * (in.n - 1) : (u128)in.n * (in.n - 1) / 2;
-    if (N128 >= ((u128)1 << 53)) return KG_ERANGE;
     if (in.directed ? (in.chunks > (1u << 31)) : (in.chunks > (1u << 15))) return KG_ERANGE;
-    const uint64_t N = (uint64_t)N128;
+    const uint64_t N = (uint64_t)N128;     // < 2^64 since n <= 2^32
     if (in.model == KG_GNM && in.m > N) return KG_EINVAL;
     if (in.model == KG_GNP && !(in.p >= 0.0 && in.p <= 1.0)) return KG_EINVAL;
+    if (N128 >= ((u128)1 << 53)) {
+        // universes of 2^53 slots and more: counts stay below 2^53 (the
+        // variates convert them exactly); slot counts round to nearest
+        if (in.model == KG_GNM && in.m >= (1ull << 53)) return KG_ERANGE;
+        if (in.model == KG_GNP && (double)N * in.p >= 0x1p52) return KG_ERANGE;
+    }
     // tile exponent: smallest s in [9, 32] with 2^s m >= lambda N (G(n,m)) or
     // 2^s p >= lambda (G(n,p))
     uint32_t s = 32;
@@ -172,6 +178,13 @@ kg_status plan_instance(const kg_instance &in, Inst &out, uint64_t &tile_bound)
         const bool ok = in.model == KG_GNM ? (((u128)in.m << t) >= (u128)kLambda * N)
                                             : (ldexp(in.p, (int)t) >= (double)kLambda);
         if (ok) { s = t; break; }
+    }
+    {
+        // every chunk has fewer than 2^31 tiles (the tile index is a 32-bit
+        // stream word): bounded through the largest section
+        const uint64_t rows = (in.n + in.chunks - 1) / in.chunks;
+        const u128 Nc = in.directed ? (u128)rows * (in.n - 1) : (u128)rows * rows;
+        if ((Nc >> s) >= ((u128)1 << 31)) return KG_ERANGE;
     }
     memset(&out, 0, sizeof(out));
     out.n = in.n;
@@ -478,6 +491,51 @@ RggLayout rgg_layout(uint64_t n, double r)
     return Y;
 }
 
+uint32_t rgg3_level(uint64_t n, double r)
+{
+    uint32_t L = 0;
+    while (L < kRgg3MaxLevel && ldexp(r, (int)L + 1) <= 1.0 && (1ull << (3 * (L + 1))) <= n) ++L;
+    return L;
+}
+
+struct Rgg3Layout {
+    uint32_t L;
+    uint64_t C, nw, nbc, nbw;
+    uint64_t tree, coff, pcell, ecnt, wsum, woff, sums, status, total;
+};
+
+Rgg3Layout rgg3_layout(uint64_t n, double r)
+{
+    Rgg3Layout Y;
+    Y.L = rgg3_level(n, r);
+    Y.C = 1ull << (3 * Y.L);
+    Y.nw = (n + 63) / 64;
+    Y.nbc = (Y.C + kScanTile - 1) / kScanTile;
+    Y.nbw = Y.nw ? (Y.nw + kScanTile - 1) / kScanTile : 1;
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) { const uint64_t at = o; o += (bytes + 255) & ~255ull; return at; };
+    Y.tree = take(((1ull << (3 * (Y.L + 1))) - 1) / 7 * 8);
+    Y.coff = take((Y.C + 1) * 8);
+    Y.pcell = take(n * 4);
+    Y.ecnt = take(n * 4);
+    Y.wsum = take((Y.nw + 1) * 8);
+    Y.woff = take((Y.nw + 1) * 8);
+    Y.sums = take((std::max(Y.nbc, Y.nbw) + 1) * 8);
+    Y.status = take(4 * 8);
+    Y.total = o;
+    return Y;
+}
+
+kg_status rgg3_check(uint64_t n, double r)
+{
+    if (!(r >= 0.0)) return KG_EINVAL;
+    if (n > 0xFFFFFFFFull) return KG_ERANGE;
+    const uint32_t L = rgg3_level(n, r);
+    // points per cell times points: the per-point pass's work
+    if ((double)n * (double)n > ldexp(1.0, 36 + 3 * (int)L)) return KG_ERANGE;
+    return KG_OK;
+}
+
 kg_status rgg_check(uint64_t n, double r)
 {
     if (!(r >= 0.0)) return KG_EINVAL;
@@ -743,6 +801,90 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
     {
         KernelTimer tm(KG_KERNEL_SAMPLE, s);
         hipLaunchKernelGGL(rgg_edges_kernel<true>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
+    }
+    if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+    release(ws, s);
+    return st;
+}
+
+kg_status kg_rgg3d_workspace_bytes(uint64_t n, double r, uint64_t *bytes)
+{
+    if (!bytes) return KG_EINVAL;
+    const kg_status st = rgg3_check(n, r);
+    if (st) return st;
+    *bytes = rgg3_layout(n, r).total;
+    return KG_OK;
+}
+
+kg_status kg_rgg3d(uint64_t n, double r, uint64_t seed, double *d_points, uint32_t *d_edges,
+                   uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
+                   void *stream)
+{
+    kg_status st = rgg3_check(n, r);
+    if (st) return st;
+    if (n > 0 && !d_points) return KG_EINVAL;
+    if (((uintptr_t)d_points & 7) != 0 || ((uintptr_t)d_edges & 7) != 0) return KG_EINVAL;
+    if (!d_edges) capacity_edges = 0;
+    hipStream_t s = (hipStream_t)stream;
+    registered_workspace(d_workspace, workspace_bytes);
+    st = capture_check(s, d_workspace);
+    if (st) return st;
+    int dev = 0;
+    st = ensure_init(&dev);
+    if (st) return st;
+    const Rgg3Layout Y = rgg3_layout(n, r);
+    Workspace ws;
+    st = acquire(ws, d_workspace, workspace_bytes, Y.total, s);
+    if (st) return st;
+    Rgg3Job J;
+    memset(&J, 0, sizeof(J));
+    J.n = n;
+    J.seed = seed;
+    J.capacity = capacity_edges;
+    J.r2 = r * r;
+    J.h = ldexp(1.0, -(int)Y.L);
+    J.L = Y.L;
+    J.G = 1u << Y.L;
+    J.C = Y.C;
+    J.tree = (uint64_t *)(ws.base + Y.tree);
+    J.coff = (uint64_t *)(ws.base + Y.coff);
+    J.pcell = (uint32_t *)(ws.base + Y.pcell);
+    J.ecnt = (uint32_t *)(ws.base + Y.ecnt);
+    J.wsum = (uint64_t *)(ws.base + Y.wsum);
+    J.woff = (uint64_t *)(ws.base + Y.woff);
+    J.sums = (uint64_t *)(ws.base + Y.sums);
+    J.status = (uint64_t *)(ws.base + Y.status);
+    J.out_total = d_total;
+    J.pts = d_points;
+    J.edges = (uint2 *)d_edges;
+    {
+        KernelTimer tm(KG_KERNEL_COUNT, s);
+        hipLaunchKernelGGL(rgg3_root_kernel, dim3(1), dim3(64), 0, s, J);
+        for (uint32_t l = 0; l < Y.L; ++l)
+            hipLaunchKernelGGL(rgg3_split_kernel, dim3((uint32_t)(((1ull << (3 * l)) + 63) / 64)), dim3(64), 0, s,
+                               J, l);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SCAN, s);
+        rgg_scan(J.tree + ((Y.C - 1) / 7), Y.C, J.sums, J.coff, s);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_QUEUE, s);
+        hipLaunchKernelGGL(rgg3_points_kernel, dim3((uint32_t)((Y.C + 63) / 64)), dim3(64), 0, s, J);
+    }
+    const uint64_t nwg = Y.nw ? Y.nw : 1;
+    {
+        KernelTimer tm(KG_KERNEL_PLAN, s);
+        hipLaunchKernelGGL(rgg3_edges_kernel<false>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SCAN, s);
+        rgg_scan(J.wsum, Y.nw, J.sums, J.woff, s);
+        hipLaunchKernelGGL(rgg3_total_kernel, dim3(1), dim3(64), 0, s, J, Y.nw);
+    }
+    {
+        KernelTimer tm(KG_KERNEL_SAMPLE, s);
+        hipLaunchKernelGGL(rgg3_edges_kernel<true>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
     }
     if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
     release(ws, s);

@@ -65,14 +65,22 @@ def test_workspace_bytes_and_validation(L):
            dict(model=1, p=1.5), dict(model=1, p=-0.1), dict(model=1, p=float("nan"))]
     for kw in bad:
         assert L.kg_workspace_bytes(ctypes.byref(_inst(**kw)), 1, ctypes.byref(out)) == _lib.KG_EINVAL, kw
-    rng = [dict(n=2**32 + 1, chunks=1, m=0), dict(n=94906267, m=0), dict(n=134217729, directed=0, m=0),
-           dict(n=2**16, directed=0, chunks=2**15 + 1, m=0)]
+    N27 = 2**27 * (2**27 - 1)                        # a directed universe above 2^53
+    rng = [dict(n=2**32 + 1, chunks=1, m=0),
+           dict(n=2**16, directed=0, chunks=2**15 + 1, m=0),
+           dict(n=2**27, m=2**53, chunks=2**10),            # N >= 2^53: the count must stay below 2^53
+           dict(n=2**27, model=1, p=2.0**52 / N27, chunks=2**10),
+           dict(n=2**32, m=0, chunks=1),                    # one chunk of 2^32 - 1 tiles of 2^32 slots
+           dict(n=2**32, directed=0, m=0, chunks=1)]
     for kw in rng:
         assert L.kg_workspace_bytes(ctypes.byref(_inst(**kw)), 1, ctypes.byref(out)) == _lib.KG_ERANGE, kw
-    # the largest sizes that still fit
-    assert L.kg_workspace_bytes(ctypes.byref(_inst(n=94906266, m=0, chunks=1)), 1, ctypes.byref(out)) == 0
-    assert L.kg_workspace_bytes(ctypes.byref(_inst(n=134217728, directed=0, m=0, chunks=1)), 1,
-                                ctypes.byref(out)) == 0
+    # universes of 2^53 slots and more are accepted (n <= 2^32, N < 2^64)
+    ok = [dict(n=94906267, m=0, chunks=4), dict(n=134217729, directed=0, m=0, chunks=4),
+          dict(n=2**27, m=2**31, chunks=2**10), dict(n=2**27, m=2**53 - 1, chunks=2**16),
+          dict(n=2**27, model=1, p=16.0 / (2**27 - 1), chunks=2**10),
+          dict(n=2**32, m=2**40, chunks=2**8), dict(n=2**32, directed=0, m=2**40, chunks=2**8)]
+    for kw in ok:
+        assert L.kg_workspace_bytes(ctypes.byref(_inst(**kw)), 1, ctypes.byref(out)) == 0, kw
 
 
 def test_view_flags(L):
