@@ -16,6 +16,7 @@ namespace kg {
 struct Job {
     uint32_t ninst;
     uint32_t leaf_cap;       // samples sorted per LDS pass, <= kCapMax
+    uint32_t fast_cap;       // draws of the register base case (tile_kernel); larger tiles are queued
     uint32_t unit_log;       // planner units hold <= 2^unit_log tiles (launch shape only)
     uint64_t G;              // chunks over all instances
     uint64_t capacity;       // output room in edges

@@ -313,6 +313,9 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     if (cap > kCapMax) cap = kCapMax;
     if (cap < 128) cap = 128;
     job.leaf_cap = (uint32_t)cap;
+    // a leaf capacity set by the caller also bounds the register base case
+    // (tests force the general path with it); by default it takes all it can
+    job.fast_cap = g_leaf_cap > 0 ? (uint32_t)std::min<int64_t>(cap, kFastDraws) : kFastDraws;
     // planner units: enough of them to give every resident lane one (one lane
     // expands a unit), at most kUnitTiles tiles each
     {

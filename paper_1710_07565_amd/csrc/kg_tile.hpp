@@ -15,8 +15,9 @@
 
 namespace kg {
 
-constexpr uint32_t kFastDraws = 832;    // draws of one wave's base case (at most 4 Philox blocks per lane)
-constexpr uint32_t kKeyWords = 896;     // LDS key words: >= kFastDraws + 3 and >= the widest sort span (64 x 14)
+constexpr uint32_t kFastDraws = 1280;   // draws of one wave's base case (at most 5 Philox blocks per lane)
+constexpr uint32_t kFastRounds = 5;     // rounds of 256 draws (one Philox block per lane each)
+constexpr uint32_t kKeyWords = 1288;    // LDS key words: >= kFastDraws + 3 and >= the widest sort span (64 x 20)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // Wave-uniform 64-bit load through the scalar data cache.  Only for data
@@ -251,9 +252,9 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         uint64_t coll = 0;      // a valid key equal to ~0 (2^32-slot tiles only)
         bool hit = false;
         // the draws stay in registers (x[4 e + q] = draw 256 e + 4 lane + q)
-        uint32_t x[16], rk[16];
+        uint32_t x[4 * kFastRounds], rk[4 * kFastRounds];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < (int)kFastRounds; ++e) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) { x[4 * e + q] = kNone; rk[4 * e + q] = 0; }
             const uint32_t blk = lane + 64u * e;
@@ -320,7 +321,7 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         __syncthreads();
         {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < (int)kFastRounds; ++e) {
                 if ((uint32_t)e < nclean) {
                     // every entry of a clean round is a valid key
                     uint32_t old[4];
@@ -355,15 +356,18 @@ __device__ __forceinline__ bool fast_set(const TileCtx &t, uint32_t *s, uint32_t
         if (R > kMaxRounds) return false;
         uint32_t ndup;
         {
-            // keys per lane from V: 8, 10, 12 or 14; [V, 64 W) is padded with ~0
-            const int mode = V <= 512 ? 0 : V <= 640 ? 1 : V <= 768 ? 2 : 3;
-            const uint32_t span = mode == 0 ? 512 : mode == 1 ? 640 : mode == 2 ? 768 : 896;
+            // keys per lane from V: 4, 8, 12, 16, 18 or 20; [V, 64 W) is padded with ~0
+            const int mode = V <= 256 ? 0 : V <= 512 ? 1 : V <= 768 ? 2 : V <= 1024 ? 3 : V <= 1152 ? 4 : 5;
+            constexpr uint32_t kSpan[6] = {256, 512, 768, 1024, 1152, 1280};
+            const uint32_t span = kSpan[mode];
             for (uint32_t p = V + lane; p < span; p += 64) s[p] = kNone;
             __syncthreads();
-            if (mode == 0) ndup = oddeven<8>(s, V, R);
-            else if (mode == 1) ndup = oddeven<10>(s, V, R);
+            if (mode == 0) ndup = oddeven<4>(s, V, R);
+            else if (mode == 1) ndup = oddeven<8>(s, V, R);
             else if (mode == 2) ndup = oddeven<12>(s, V, R);
-            else ndup = oddeven<14>(s, V, R);
+            else if (mode == 3) ndup = oddeven<16>(s, V, R);
+            else if (mode == 4) ndup = oddeven<18>(s, V, R);
+            else ndup = oddeven<20>(s, V, R);
             __syncthreads();
         }
         const uint32_t D = V - ndup;
@@ -502,9 +506,9 @@ __device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t
     t1 = t0 + per < T ? t0 + per : T;
 }
 
-// 6 waves per SIMD (at most 80 VGPRs; a few cold values spill to scratch)
-// run faster than 5 waves without spills or 7 waves with many
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void tile_kernel(Job job)
+// 5 waves per SIMD: the LDS of a wave (keys of up to 1280 draws and 512
+// bucket counters, 7.2 KB) allows no more, and leaves 102 VGPRs
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void tile_kernel(Job job)
 {
     __shared__ __attribute__((aligned(16))) uint32_t s_key[kKeyWords];
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // bucket counters, then starts
@@ -519,7 +523,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         cw[1] = make_uint4(0, 0, 0, 0);
         __syncthreads();
     }
-    const uint32_t lim = job.leaf_cap < kFastDraws ? job.leaf_cap : kFastDraws;
+    const uint32_t lim = job.fast_cap < kFastDraws ? job.fast_cap : kFastDraws;
     // chunk of the first tile: last g with tstart[g] <= t
     uint64_t g;
     {

@@ -119,14 +119,14 @@ def test_generation_calls_reject_bad_arguments_without_a_device(L):
 
 
 def test_oracle_tile_exponent_is_minimal(kgref):
-    """The tile exponent is the smallest s in [9, 32] with 2^s m >= 362 N
-    (tiles hold 362..724 samples in expectation)."""
+    """The tile exponent is the smallest s in [9, 32] with 2^s m >= 724 N
+    (tiles hold 724..1448 samples in expectation)."""
     for n, m in [(2**16, 2**20), (2**10, 2**19), (50, 1225), (2**20, 5)]:
         I = kgref.inst(n, m=m, directed=True, seed=1, chunks=1)
         s = kgref.tile_exponent(I)
         N = n * (n - 1)
-        assert (m << s) >= 362 * N or s == 32
-        assert s == 9 or (m << (s - 1)) < 362 * N
+        assert (m << s) >= 724 * N or s == 32
+        assert s == 9 or (m << (s - 1)) < 724 * N
 
 
 def test_skip_variant_argument_checks(L):
@@ -201,16 +201,16 @@ def test_set_workspace_argument_checks(L):
 
 
 @pytest.mark.parametrize("n,m,p,directed,P,s_want", [
-    (2**16, 2**20, 0.0, True, 64, 21),                 # small directed G(n,m)
-    (2**26, 2**31, 0.0, False, 256, 29),               # headline undirected G(n,m)
-    (2**25, 0, 16.0 / (2**25 - 1), True, 2**16, 30),   # directed G(n,p), mean out-degree 16
-    (2**25, 0, 64.0 / (2**25 - 1), False, 256, 28),    # undirected G(n,p), mean degree 64
+    (2**16, 2**20, 0.0, True, 64, 22),                 # small directed G(n,m)
+    (2**26, 2**31, 0.0, False, 256, 30),               # headline undirected G(n,m)
+    (2**25, 0, 16.0 / (2**25 - 1), True, 2**16, 31),   # directed G(n,p), mean out-degree 16
+    (2**25, 0, 64.0 / (2**25 - 1), False, 256, 29),    # undirected G(n,p), mean degree 64
 ])
 def test_tile_exponent_of_the_workloads(kgref, n, m, p, directed, P, s_want):
     """The tile exponent of each benchmark workload, checked against the
     sampling threshold's definition written out here: the expected samples
-    of a full tile, 2^s m / N (G(n,m)) or 2^s p (G(n,p)), reach 362 at s and
-    not at s - 1; every one of these workloads lands within 0.01 of 512."""
+    of a full tile, 2^s m / N (G(n,m)) or 2^s p (G(n,p)), reach 724 at s and
+    not at s - 1; every one of these workloads lands within 0.02 of 1024."""
     from fractions import Fraction
     model = 0 if p == 0.0 else 1
     I = kgref.inst(n, m=m, p=p, directed=directed, seed=1, chunks=P, model=model)
@@ -218,5 +218,5 @@ def test_tile_exponent_of_the_workloads(kgref, n, m, p, directed, P, s_want):
     assert s == s_want
     N = n * (n - 1) // (1 if directed else 2)
     mean = (lambda t: Fraction(m * 2**t, N)) if model == 0 else (lambda t: Fraction(p) * 2**t)
-    assert mean(s) >= 362 and mean(s - 1) < 362
-    assert abs(float(mean(s)) - 512.0) < 0.01
+    assert mean(s) >= 724 and mean(s - 1) < 724
+    assert abs(float(mean(s)) - 1024.0) < 0.02

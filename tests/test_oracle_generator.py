@@ -99,7 +99,7 @@ def test_gnp_graph_probabilities(kgref, directed, n):
 def test_config_small_directed_invariants(kgref):
     # directed G(n,m), n=2^16, m=2^20, 64 chunks, seed 1
     I = kgref.inst(2**16, m=2**20, directed=True, seed=1, chunks=64)
-    assert kgref.tile_exponent(I) == 21
+    assert kgref.tile_exponent(I) == 22
     E = kgref.generate(I)
     check_invariants(kgref, I, E)
 
@@ -239,19 +239,21 @@ def test_degree_laws(kgref):
 
 def test_tile_counts_sum_and_law(kgref):
     I = kgref.inst(2**16, m=2**20, directed=True, seed=1, chunks=64)
+    s = kgref.tile_exponent(I)
+    assert s == 22
+    Nc = 1024 * (2**16 - 1)
     counts = kgref.chunk_counts(I)
     for c in [0, 17, 63]:
         tc = kgref.tile_counts(I, c, counts[c])
         assert tc.sum() == counts[c]
-        assert len(tc) == 32
+        assert len(tc) == -(-Nc // 2**s)              # ceil(N_c / 2^s) tiles, the last partial
     # tile 0 of chunk 0 across seeds ~ Hyp(N_c, S, K_c) given K_c: check mean
     vals = []
     for seed in range(300):
         J = kgref.inst(2**16, m=2**20, directed=True, seed=seed, chunks=64)
         Kc = kgref.chunk_count_path(J, 0)
-        Nc = 1024 * (2**16 - 1)
         tc = kgref.tile_counts(J, 0, Kc)
-        vals.append((tc[0] - Kc * 2**21 / Nc) / math.sqrt(Kc * 2**21 / Nc))
+        vals.append((tc[0] - Kc * 2**s / Nc) / math.sqrt(Kc * 2**s / Nc))
     assert abs(np.mean(vals)) < 5 / math.sqrt(300)
 
 
@@ -289,20 +291,20 @@ def test_gnp_geometric_skip_cross_check(kgref):
 
 
 def test_uneven_tile_tree_marginals(kgref):
-    """n=100 directed, m=1500, one chunk: tiles of 2^12 slots -> sizes 4096,
+    """n=100 directed, m=3000, one chunk: tiles of 2^12 slots -> sizes 4096,
     4096, 1708 (the root splits [0,2) | [2,3)).  Each tile count must follow
-    Hyp(9900, size, 1500); a swapped split would move tile 2's mean from
-    258.8 to 620.6."""
-    I0 = kgref.inst(100, m=1500, directed=True, seed=1, chunks=1)
+    Hyp(9900, size, 3000); a swapped split would move tile 2's mean from
+    517.6 to 1241.2."""
+    I0 = kgref.inst(100, m=3000, directed=True, seed=1, chunks=1)
     assert kgref.tile_exponent(I0) == 12
     reps = 3000
     tc = np.zeros((reps, 3), dtype=np.int64)
     for s in range(reps):
-        I = kgref.inst(100, m=1500, directed=True, seed=s, chunks=1)
-        tc[s] = kgref.tile_counts(I, 0, 1500)
-    assert np.all(tc.sum(axis=1) == 1500)
+        I = kgref.inst(100, m=3000, directed=True, seed=s, chunks=1)
+        tc[s] = kgref.tile_counts(I, 0, 3000)
+    assert np.all(tc.sum(axis=1) == 3000)
     for t, size in enumerate([4096, 4096, 1708]):
-        rv = stats.hypergeom(9900, size, 1500)
+        rv = stats.hypergeom(9900, size, 3000)
         assert _degree_chi2(tc[:, t], rv) > 1e-5, t
 
 
