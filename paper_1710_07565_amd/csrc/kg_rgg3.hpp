@@ -220,16 +220,31 @@ __global__ __launch_bounds__(64) void rgg3_edges_kernel(Rgg3Job J)
             const uint32_t zz = nb[i];
             if (zz == kRggNone) continue;
             const uint64_t b1 = J.coff[zz + 1];
-            for (uint64_t b = zz == z ? u + 1 : J.coff[zz]; b < b1; ++b) {
-                const double *q = J.pts + 3 * b;
-                const double dx = px - q[0], dy = py - q[1], dz = pz - q[2];
-                if ((dx * dx + dy * dy) + dz * dz < r2) {
-                    if (WRITE) {
-                        const uint2 e = make_uint2((uint32_t)u, (uint32_t)b);
-                        if (staged) s_e[lo + cnt] = e;
-                        else J.edges[o + lo + cnt] = e;
+            // four candidates' loads in flight per trip (a cell holds a few
+            // points, so most cells take one trip)
+            for (uint64_t b = zz == z ? u + 1 : J.coff[zz]; b < b1; b += 4) {
+                double q[4][3];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (b + t < b1) {
+                        const double *src = J.pts + 3 * (b + t);
+                        q[t][0] = src[0];
+                        q[t][1] = src[1];
+                        q[t][2] = src[2];
                     }
-                    ++cnt;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (b + t >= b1) break;
+                    const double dx = px - q[t][0], dy = py - q[t][1], dz = pz - q[t][2];
+                    if ((dx * dx + dy * dy) + dz * dz < r2) {
+                        if (WRITE) {
+                            const uint2 e = make_uint2((uint32_t)u, (uint32_t)(b + t));
+                            if (staged) s_e[lo + cnt] = e;
+                            else J.edges[o + lo + cnt] = e;
+                        }
+                        ++cnt;
+                    }
                 }
             }
         }
