@@ -504,7 +504,7 @@ uint32_t rgg3_level(uint64_t n, double r)
 struct Rgg3Layout {
     uint32_t L;
     uint64_t C, nw, nbc, nbw;
-    uint64_t tree, coff, pcell, ecnt, wsum, woff, sums, status, total;
+    uint64_t tree, coff, pcell, ecnt, bits, wsum, woff, sums, status, total;
 };
 
 Rgg3Layout rgg3_layout(uint64_t n, double r)
@@ -521,6 +521,7 @@ Rgg3Layout rgg3_layout(uint64_t n, double r)
     Y.coff = take((Y.C + 1) * 8);
     Y.pcell = take(n * 4);
     Y.ecnt = take(n * 4);
+    Y.bits = take(n * 8 * kRgg3BitWords);
     Y.wsum = take((Y.nw + 1) * 8);
     Y.woff = take((Y.nw + 1) * 8);
     Y.sums = take((std::max(Y.nbc, Y.nbw) + 1) * 8);
@@ -853,6 +854,7 @@ kg_status kg_rgg3d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
     J.coff = (uint64_t *)(ws.base + Y.coff);
     J.pcell = (uint32_t *)(ws.base + Y.pcell);
     J.ecnt = (uint32_t *)(ws.base + Y.ecnt);
+    J.bits = (uint64_t *)(ws.base + Y.bits);
     J.wsum = (uint64_t *)(ws.base + Y.wsum);
     J.woff = (uint64_t *)(ws.base + Y.woff);
     J.sums = (uint64_t *)(ws.base + Y.sums);

@@ -30,6 +30,7 @@ constexpr uint32_t TAG_RTREE3 = 10;
 constexpr uint32_t TAG_RPTS3 = 11;
 constexpr uint32_t kRgg3MaxLevel = 10;     // 8^10 cells: Morton indices below 2^30
 constexpr uint32_t kRgg3Win = 27;          // cells of a 3 x 3 x 3 window
+constexpr uint32_t kRgg3BitWords = 2;      // candidates recorded per vertex: 128 (about 54 on average)
 
 struct Rgg3Job {
     uint64_t n, seed, capacity;
@@ -39,7 +40,8 @@ struct Rgg3Job {
     uint64_t *tree;            // node counts, level l at (8^l - 1) / 7, Morton order
     uint64_t *coff;            // C + 1 first vertex id of every cell
     uint32_t *pcell;           // n: cell of every vertex
-    uint32_t *ecnt;            // n: edges (u, v > u) of every vertex u
+    uint32_t *ecnt;            // n: edges (u, v > u) of every vertex u; top bit: more candidates than recorded
+    uint64_t *bits;            // kRgg3BitWords x n (word-major): the count pass's test results per candidate
     uint64_t *wsum;            // ceil(n / 64) + 1: edges per wave of vertices, then their offsets
     uint64_t *woff;
     uint64_t *sums;            // scan partials
@@ -167,10 +169,13 @@ __device__ __forceinline__ void rgg3_window(uint32_t z, uint32_t G, uint32_t (&n
 // hold the ids above u's cell in ascending order; within u's own cell the
 // candidates start at u + 1.  The windows of the (at most 64) cells a wave's
 // vertices lie in are sorted once, one lane per cell, into LDS.  Count pass
-// (WRITE = false): per-vertex and per-wave edge counts.  Write pass: the same
-// walk, the edges stored at the wave's offset plus the in-wave prefix,
-// gathered in LDS and stored with consecutive lanes on consecutive edges
-// unless they exceed the buffer.
+// (WRITE = false): per-vertex and per-wave edge counts, and the results of
+// the vertex's first 128 candidate tests as a bit mask (word-major, so a
+// wave's stores are contiguous; a vertex with more candidates is flagged).
+// Write pass: the same walk reading the mask (flagged vertices test again),
+// the edges stored at the wave's offset plus the in-wave prefix, gathered in
+// LDS and stored with consecutive lanes on consecutive edges unless they
+// exceed the buffer.
 template <bool WRITE>
 __global__ __launch_bounds__(64) void rgg3_edges_kernel(Rgg3Job J)
 {
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(64) void rgg3_edges_kernel(Rgg3Job J)
     uint64_t o = 0, wtotal = 0, lo = 0;
     if (WRITE) {
         if (J.status[1]) return;
-        const uint64_t k = u < J.n ? J.ecnt[u] : 0;
+        const uint64_t k = u < J.n ? (J.ecnt[u] & ~kRggMore) : 0;
         const uint64_t incl = wave_incl_scan64(k);
         lo = incl - k;
         wtotal = __shfl(incl, 63, 64);
@@ -192,65 +197,117 @@ __global__ __launch_bounds__(64) void rgg3_edges_kernel(Rgg3Job J)
     // (a wave without vertices -- n = 0 -- only stores its zero sum)
     const uint64_t ul = u0 + 63 < J.n ? u0 + 63 : J.n - 1;
     const uint32_t zlo = u0 < J.n ? J.pcell[u0] : 0, zhi = u0 < J.n ? J.pcell[ul] : 0;
+    // the windows in LDS: one per cell of the wave (sorted once per cell), or,
+    // when the wave's vertices spread over more than 64 cells, one per lane
     const bool shared = u0 < J.n && zhi - zlo < 64;
-    if (shared) {
-        if (lane <= zhi - zlo) {
+    if (u0 < J.n) {
+        const bool mine = shared ? lane <= zhi - zlo : u < J.n;
+        if (mine) {
             uint32_t nb[kRgg3Win];
-            rgg3_window(zlo + lane, J.G, nb);
+            rgg3_window(shared ? zlo + lane : J.pcell[u], J.G, nb);
 #pragma unroll
             for (int i = 0; i < 27; ++i) s_win[lane][i] = nb[i];
         }
         __syncthreads();
     }
     uint32_t cnt = 0;
+    uint64_t c = 0;       // candidates seen
+    bool more = false;
+    if (WRITE && u < J.n) more = (J.ecnt[u] & kRggMore) != 0;
     if (u < J.n) {
         const uint32_t z = J.pcell[u];
-        uint32_t nb[kRgg3Win];
-        if (shared) {
+        const uint32_t *nb = s_win[shared ? z - zlo : lane];
+        auto emit = [&](uint64_t b) {
+            const uint2 e = make_uint2((uint32_t)u, (uint32_t)b);
+            if (staged) s_e[lo + cnt] = e;
+            else J.edges[o + lo + cnt] = e;
+            ++cnt;
+        };
+        if (!WRITE || more) {
+            const double *p = J.pts + 3 * u;
+            const double px = p[0], py = p[1], pz = p[2];
+            const double r2 = J.r2;
+            uint64_t cur = 0;
+            // count pass: append nbits (1..4) result bits v to the vertex's
+            // mask; a full word is stored if recorded, a word boundary inside
+            // v carries over
+            auto put = [&](uint32_t v, uint32_t nbits) {
+                const uint32_t off = (uint32_t)(c & 63);
+                const uint64_t w = c >> 6;
+                cur |= (uint64_t)v << off;
+                c += nbits;
+                if (off + nbits >= 64) {
+                    if (w < kRgg3BitWords) J.bits[w * J.n + u] = cur;
+                    cur = off + nbits > 64 ? (uint64_t)(v >> (64 - off)) : 0;
+                }
+            };
 #pragma unroll
-            for (int i = 0; i < 27; ++i) nb[i] = s_win[z - zlo][i];
-        } else {
-            rgg3_window(z, J.G, nb);
-        }
-        const double *p = J.pts + 3 * u;
-        const double px = p[0], py = p[1], pz = p[2];
-        const double r2 = J.r2;
+            for (int i = 0; i < 27; ++i) {
+                const uint32_t zz = nb[i];
+                if (zz == kRggNone) continue;
+                const uint64_t b1 = J.coff[zz + 1];
+                // four candidates' loads in flight per trip (a cell holds a
+                // few points, so most cells take one trip)
+                for (uint64_t b = zz == z ? u + 1 : J.coff[zz]; b < b1; b += 4) {
+                    double q[4][3];
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const uint32_t zz = nb[i];
-            if (zz == kRggNone) continue;
-            const uint64_t b1 = J.coff[zz + 1];
-            // four candidates' loads in flight per trip (a cell holds a few
-            // points, so most cells take one trip)
-            for (uint64_t b = zz == z ? u + 1 : J.coff[zz]; b < b1; b += 4) {
-                double q[4][3];
+                    for (int t = 0; t < 4; ++t) {
+                        if (b + t < b1) {
+                            const double *src = J.pts + 3 * (b + t);
+                            q[t][0] = src[0];
+                            q[t][1] = src[1];
+                            q[t][2] = src[2];
+                        }
+                    }
+                    uint32_t v = 0;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (b + t < b1) {
-                        const double *src = J.pts + 3 * (b + t);
-                        q[t][0] = src[0];
-                        q[t][1] = src[1];
-                        q[t][2] = src[2];
+                    for (int t = 0; t < 4; ++t) {
+                        if (b + t >= b1) break;
+                        const double dx = px - q[t][0], dy = py - q[t][1], dz = pz - q[t][2];
+                        if ((dx * dx + dy * dy) + dz * dz < r2) {
+                            if (WRITE) emit(b + t);
+                            else v |= 1u << t;
+                        }
+                    }
+                    if (!WRITE) {
+                        cnt += (uint32_t)__builtin_popcount(v);
+                        put(v, (uint32_t)min((uint64_t)4, b1 - b));
                     }
                 }
+            }
+            if (!WRITE && (c & 63) != 0 && (c >> 6) < kRgg3BitWords) J.bits[(c >> 6) * J.n + u] = cur;
+        } else {
+            // the recorded results: walk the candidates in the same order, a
+            // word at a time, and emit the set bits
+            uint32_t wcur = kRggNone;
+            uint64_t word = 0;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (b + t >= b1) break;
-                    const double dx = px - q[t][0], dy = py - q[t][1], dz = pz - q[t][2];
-                    if ((dx * dx + dy * dy) + dz * dz < r2) {
-                        if (WRITE) {
-                            const uint2 e = make_uint2((uint32_t)u, (uint32_t)(b + t));
-                            if (staged) s_e[lo + cnt] = e;
-                            else J.edges[o + lo + cnt] = e;
-                        }
-                        ++cnt;
+            for (int i = 0; i < 27; ++i) {
+                const uint32_t zz = nb[i];
+                if (zz == kRggNone) continue;
+                const uint64_t b1 = J.coff[zz + 1];
+                uint64_t b = zz == z ? u + 1 : J.coff[zz];
+                while (b < b1) {
+                    const uint32_t w = (uint32_t)(c >> 6), off = (uint32_t)(c & 63);
+                    if (w != wcur) {
+                        word = J.bits[(uint64_t)w * J.n + u];
+                        wcur = w;
                     }
+                    const uint64_t take = min((uint64_t)(64 - off), b1 - b);
+                    uint64_t m = word >> off;
+                    if (take < 64) m &= (1ull << take) - 1;
+                    while (m) {
+                        emit(b + (uint64_t)__builtin_ctzll(m));
+                        m &= m - 1;
+                    }
+                    b += take;
+                    c += take;
                 }
             }
         }
     }
     if (!WRITE) {
-        if (u < J.n) J.ecnt[u] = cnt;
+        if (u < J.n) J.ecnt[u] = cnt | (c > 64ull * kRgg3BitWords ? kRggMore : 0u);
         const uint64_t incl = wave_incl_scan64((uint64_t)cnt);
         if (lane == 63) J.wsum[blockIdx.x] = incl;
     } else if (staged) {
