@@ -811,6 +811,8 @@ def main():
                     help="no run: read rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of a profiled "
                          "run of this workload (with --calibrate-copy-gib) and record the tile_kernel HBM traffic "
                          "in profiles/tile_kernel_traffic.json")
+    ap.add_argument("--count-lanes", type=int, default=0, choices=[0, 1, 4, 8],
+                    help="lanes per chunk in the count kernel (0: the library's choice; launch shape only)")
     ap.add_argument("--traffic-command", action="append", default=[],
                     help="the profiling commands, recorded with the traffic figure")
     args = ap.parse_args()
@@ -824,6 +826,9 @@ def main():
         print("bench.py runs on one GPU only: the generator needs no communication and this build "
               "measures a single MI355X (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.count_lanes:
+        import paper_1710_07565_amd as kg
+        kg.set_option(kg._lib.KG_OPT_COUNT_LANES, args.count_lanes)
     if args.calibrate_copy_gib > 0:
         import torch
         nb = int(args.calibrate_copy_gib * 2**30) // 4

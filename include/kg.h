@@ -277,10 +277,17 @@ enum {
     KG_OPT_LEAF_CAP = 1,        /* samples a wave sorts in LDS per pass (128..1024) */
     KG_OPT_SAMPLE_WAVES = 2,    /* resident sampler waves per compute unit (1..32) */
     KG_OPT_PLAN_WAVES = 3,      /* resident tile-planner waves per compute unit (1..64) */
-    KG_OPT_TIME_KERNELS = 4     /* 1: bracket every kernel launch with hipEvents (not under capture) */
+    KG_OPT_TIME_KERNELS = 4,    /* 1: bracket every kernel launch with hipEvents (not under capture) */
+    KG_OPT_COUNT_LANES = 5      /* lanes per chunk in the count kernel (1, 4 or 8; 0: the most for
+                                   which every workgroup of the launch is resident at once) */
 };
 kg_status kg_set_option(int option, int64_t value);
 int64_t kg_get_option(int option);
+
+/* The hipError_t code behind the most recent KG_EDEVICE that a rejected
+ * kernel launch caused on the calling thread (0 if none yet); for error
+ * messages.  Host only. */
+int kg_last_hip_error(void);
 
 /* Kernel timing for measurement.  While KG_OPT_TIME_KERNELS is 1 every launch
  * of kernel `kernel` (KG_KERNEL_*) is bracketed by two hipEvents recorded on

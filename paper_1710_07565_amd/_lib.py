@@ -13,9 +13,10 @@ KG_OPT_LEAF_CAP, KG_OPT_SAMPLE_WAVES, KG_OPT_PLAN_WAVES = 1, 2, 3
 
 EXPORTS = ["kg_spec_version", "kg_strerror", "kg_workspace_bytes", "kg_set_workspace", "kg_gnm", "kg_gnp", "kg_gnp_count",
            "kg_chunk_counts", "kg_batch", "kg_batch_upload", "kg_batch_launch", "kg_pe_view", "kg_gnp_skip",
-           "kg_rgg2d_workspace_bytes", "kg_rgg2d", "kg_rgg3d_workspace_bytes", "kg_rgg3d", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_eval",
+           "kg_rgg2d_workspace_bytes", "kg_rgg2d", "kg_rgg3d_workspace_bytes", "kg_rgg3d", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_last_hip_error", "kg_eval",
            "kg_kernel_time_read", "kg_edge_hash", "kg_gnm_static"]
 KG_OPT_TIME_KERNELS = 4
+KG_OPT_COUNT_LANES = 5
 KG_KERNEL_COUNT, KG_KERNEL_SCAN, KG_KERNEL_PLAN, KG_KERNEL_SAMPLE, KG_KERNEL_QUEUE = 0, 1, 2, 3, 4
 KG_EVAL_PHILOX, KG_EVAL_LOG, KG_EVAL_LOG1P, KG_EVAL_LNF_DIFF, KG_EVAL_HYP, KG_EVAL_BIN, KG_EVAL_SQRT_DIV = range(1, 8)
 
@@ -29,7 +30,13 @@ class KgInstance(ctypes.Structure):
 class KgError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
-        super().__init__("%s: %s (%d)" % (what, strerror(status), status))
+        msg = "%s: %s (%d)" % (what, strerror(status), status)
+        if status == KG_EDEVICE:
+            try:
+                msg += ", HIP error %d" % lib().kg_last_hip_error()
+            except Exception:
+                pass
+        super().__init__(msg)
 
 
 _lib = None
@@ -43,6 +50,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError("HIP library %s is missing: run `python -m paper_1710_07565_amd.build` "
                           "(or __graft_entry__.build())" % LIB_PATH)
+    # PyTorch ships its own HIP runtime under the soname libamdhip64.so.7 but
+    # asks for it as libamdhip64.so.  Loaded first, libkg.so would pull in the
+    # system copy and the process would hold two HIP runtimes, so that the
+    # streams and allocations the binding passes in belong to another runtime
+    # than the library's launches.  Importing torch first makes libkg.so bind
+    # to the runtime torch already holds.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     u64, u32, i32, dbl, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
     ip = ctypes.POINTER(KgInstance)
@@ -70,6 +84,7 @@ def lib():
     L.kg_instance_seed.argtypes = [u64, u32]; L.kg_instance_seed.restype = u64
     L.kg_set_option.argtypes = [ctypes.c_int, ctypes.c_int64]; L.kg_set_option.restype = i32
     L.kg_get_option.argtypes = [ctypes.c_int]; L.kg_get_option.restype = ctypes.c_int64
+    L.kg_last_hip_error.argtypes = []; L.kg_last_hip_error.restype = ctypes.c_int
     L.kg_eval.argtypes = [ctypes.c_int, vp, vp, u64, vp]; L.kg_eval.restype = i32
     L.kg_kernel_time_read.argtypes = [ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(u64)]
     L.kg_kernel_time_read.restype = i32

@@ -278,6 +278,17 @@ struct HypRatio {
         T = T + lnf_diff(N - K - k + X, N - K - k + M);
         return T;
     }
+    // the t-th difference of the sum above, and the sum in the same order
+    __device__ __forceinline__ double term(uint32_t t, uint64_t X) const
+    {
+        const uint64_t b = t == 0 ? 0 : t == 1 ? k : t == 2 ? K : N - K - k;
+        const bool up = t == 0 || t == 3;
+        return lnf_diff(up ? b + X : b - X, up ? b + M : b - M);
+    }
+    __device__ __forceinline__ double combine(double d0, double d1, double d2, double d3, uint64_t) const
+    {
+        return ((d0 + d1) + d2) + d3;
+    }
 };
 
 // log f(x) - log f(M) of the binomial law; lq = log p - log(1-p).
@@ -291,30 +302,88 @@ struct BinRatio {
         T = T + ((double)X - (double)M) * lq;
         return T;
     }
+    __device__ __forceinline__ double term(uint32_t t, uint64_t X) const
+    {
+        const bool up = t != 1;
+        const uint64_t b = t == 1 ? N : 0;
+        return t < 2 ? lnf_diff(up ? b + X : b - X, up ? b + M : b - M) : 0.0;
+    }
+    __device__ __forceinline__ double combine(double d0, double d1, double, double, uint64_t X) const
+    {
+        return (d0 + d1) + ((double)X - (double)M) * lq;
+    }
 };
 
-template <class Ratio>
+// Quad broadcast: the value of lane T of each group of four lanes, to all
+// four (DPP quad_perm; the four lanes are active together).
+template <int T>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, T * 0x55, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), T * 0x55, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// PAR = 1, TERMS = 1: one proposal at a time in one lane.  Otherwise an
+// aligned group of PAR * TERMS lanes works on one variate (the same
+// arguments in every lane of the group): it tries proposals j0 .. j0 + PAR - 1
+// at once, and with TERMS = 4 the four log-factorial differences of a
+// proposal's ratio are formed in the four lanes of a quad and summed in the
+// sequential order.  The lowest accepted proposal wins, so the variate is
+// the one the sequential loop returns.  Used where a variate's latency, not
+// the lanes' throughput, bounds a kernel.
+template <int PAR, int TERMS, class Ratio>
 __device__ __forceinline__ uint64_t rou_sample(const Stream &s, double a, double h, uint64_t upper,
                                                const Ratio &ratio)
 {
+    static_assert(PAR == 1 || PAR == 2 || PAR == 4 || PAR == 8, "1, 2, 4 or 8 proposals at once");
+    static_assert(TERMS == 1 || TERMS == 4, "ratio in one lane or in a quad");
+    constexpr uint32_t GL = PAR * TERMS;     // lanes per variate
     const double upper_excl = (double)upper + 1.0;
-    for (uint32_t j = 0;; ++j) {
-        const U4 w = s.block(j);
+    const uint32_t lane = __lane_id();
+    const uint32_t q = (lane & (GL - 1)) / TERMS;
+    const uint32_t tq = lane & (TERMS - 1);
+    for (uint32_t j0 = 0;; j0 += PAR) {
+        const U4 w = s.block(j0 + q);
         const double U = unit_of(((uint64_t)w.y << 32) | w.x);
         const double V = unit_of(((uint64_t)w.w << 32) | w.z);
         const double t = a + h * (V - 0.5) / U;
-        if (!(t >= 0.0) || t >= upper_excl) continue;
-        const uint64_t X = (uint64_t)floor(t);
-        if (X > upper) continue;        // upper + 1 rounds in binary64 above 2^53
-        const double T = ratio(X);
-        if (U * (4.0 - U) - 3.0 <= T) return X;
-        if (U * (U - T) >= 1.0) continue;
-        if (2.0 * log_f64(U) <= T) return X;
+        bool acc = false;
+        uint64_t X = 0;
+        if (t >= 0.0 && t < upper_excl) {
+            X = (uint64_t)floor(t);
+            if (X <= upper) {           // upper + 1 rounds in binary64 above 2^53
+                double T;
+                if (TERMS == 1) {
+                    T = ratio(X);
+                } else {
+                    const double d = ratio.term(tq, X);
+                    T = ratio.combine(quad_bcast<0>(d), quad_bcast<1>(d), quad_bcast<2>(d), quad_bcast<3>(d), X);
+                }
+                if (U * (4.0 - U) - 3.0 <= T) acc = true;
+                else if (U * (U - T) >= 1.0) acc = false;
+                else acc = 2.0 * log_f64(U) <= T;
+            }
+        }
+        if (GL == 1) {
+            if (acc) return X;
+        } else {
+            const uint32_t base = lane & ~(GL - 1);
+            const uint32_t won = (uint32_t)(__ballot(acc) >> base) & (uint32_t)((1ull << GL) - 1);
+            if (won) {
+                const int src = (int)(base + __builtin_ctz(won));
+                const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)X, src);
+                const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(X >> 32), src);
+                return ((uint64_t)hi << 32) | lo;
+            }
+        }
     }
 }
 
 // Hypergeometric: how many of k draws without replacement from N items land
 // among K marked ones (the sample size of a sub-universe, Sec. 2.2).
+template <int PAR = 1, int TERMS = 1>
 __device__ __forceinline__ uint64_t hyp(const Stream &s, uint64_t N, uint64_t K, uint64_t k)
 {
     // symmetries: complement the draws, complement the marked set, swap roles
@@ -342,7 +411,7 @@ __device__ __forceinline__ uint64_t hyp(const Stream &s, uint64_t N, uint64_t K,
         const double h = kRouD1 * c + kRouD2;
         const double a = mu + 0.5;
         HypRatio r{N, hi, lo, muldiv_floor(lo + 1, hi + 1, N + 2)};
-        x = rou_sample(s, a, h, lo, r);
+        x = rou_sample<PAR, TERMS>(s, a, h, lo, r);
     }
     if (c2) x = k1 - x;
     if (c1) x = K - x;
@@ -425,6 +494,7 @@ struct HypRun {
 
 // Binomial(N, p): a G(n,p) chunk's edge count (Sec. 4.3).  Small means by
 // geometric waiting times floor(log U / log(1-p)); otherwise ratio of uniforms.
+template <int PAR = 1, int TERMS = 1>
 __device__ __forceinline__ uint64_t bin_core(const Stream &s, uint64_t N, double p)
 {
     const double Nd = (double)N;
@@ -447,15 +517,16 @@ __device__ __forceinline__ uint64_t bin_core(const Stream &s, uint64_t N, double
     const double h = kRouD1 * c + kRouD2;
     const double a = mu + 0.5;
     BinRatio r{N, (uint64_t)floor((Nd + 1.0) * p), log_f64(p) - log1p_f64(-p)};
-    return rou_sample(s, a, h, N, r);
+    return rou_sample<PAR, TERMS>(s, a, h, N, r);
 }
 
+template <int PAR = 1, int TERMS = 1>
 __device__ __forceinline__ uint64_t binom(const Stream &s, uint64_t N, double p)
 {
     if (N == 0 || p <= 0.0) return 0;
     if (p >= 1.0) return N;
-    if (p > 0.5) return N - bin_core(s, N, 1.0 - p);
-    return bin_core(s, N, p);
+    if (p > 0.5) return N - bin_core<PAR, TERMS>(s, N, 1.0 - p);
+    return bin_core<PAR, TERMS>(s, N, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,6 +618,7 @@ __device__ __forceinline__ uint32_t unit_depth(uint64_t T, uint32_t ulog)
 // paper; Sec. 2.2, 4.1, 4.2).  The split of a range [lo, hi) of chunks or
 // sections is at lo + ceil((hi - lo)/2).
 // ---------------------------------------------------------------------------
+template <int PAR = 1, int TERMS = 1>
 __device__ __forceinline__ uint64_t dtree_count(const Inst &I, uint64_t c)
 {
     uint64_t k = I.m, lo = 0, hi = I.P;
@@ -557,7 +629,7 @@ __device__ __forceinline__ uint64_t dtree_count(const Inst &I, uint64_t c)
         const uint64_t blo = section_bound(I, lo);
         const uint64_t Nn = (section_bound(I, hi) - blo) * w;
         const uint64_t Nl = (section_bound(I, mid) - blo) * w;
-        const uint64_t X = hyp(make_stream(I.seed, heap, 0, TAG_DTREE), Nn, Nl, k);
+        const uint64_t X = hyp<PAR, TERMS>(make_stream(I.seed, heap, 0, TAG_DTREE), Nn, Nl, k);
         if (c < mid) { hi = mid; k = X; heap = 2 * heap; }
         else         { lo = mid; k = k - X; heap = 2 * heap + 1; }
     }
@@ -575,6 +647,7 @@ __device__ __forceinline__ uint64_t rect_slots(const Inst &I, uint64_t a, uint64
     return (section_bound(I, b) - section_bound(I, a)) * (section_bound(I, d) - section_bound(I, c));
 }
 
+template <int PAR = 1, int TERMS = 1>
 __device__ __forceinline__ uint64_t utree_count(const Inst &I, uint64_t ci, uint64_t cj)
 {
     uint64_t k = I.m, a = 0, b = I.P, cc = 0, d = 0;
@@ -585,9 +658,9 @@ __device__ __forceinline__ uint64_t utree_count(const Inst &I, uint64_t ci, uint
             if (b - a == 1) return k;
             const uint64_t l = a + (b - a + 1) / 2;
             const uint64_t Nn = tri_slots(I, a, b), N1 = tri_slots(I, a, l), NR = rect_slots(I, a, l, l, b);
-            const uint64_t X0 = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, N1, k);
+            const uint64_t X0 = hyp<PAR, TERMS>(make_stream(I.seed, code, 0, TAG_UTREE), Nn, N1, k);
             if (cj < l) { b = l; k = X0; code = 4 * code; continue; }
-            const uint64_t X1 = hyp(make_stream(I.seed, code, 1, TAG_UTREE), Nn - N1, NR, k - X0);
+            const uint64_t X1 = hyp<PAR, TERMS>(make_stream(I.seed, code, 1, TAG_UTREE), Nn - N1, NR, k - X0);
             if (ci < l) { tri = false; cc = l; d = b; b = l; k = X1; code = 4 * code + 1; continue; }
             a = l; k = k - X0 - X1; code = 4 * code + 2;
             continue;
@@ -596,14 +669,14 @@ __device__ __forceinline__ uint64_t utree_count(const Inst &I, uint64_t ci, uint
         const uint64_t Nn = rect_slots(I, a, b, cc, d);
         if (d - cc == 1) {
             const uint64_t l = a + (b - a + 1) / 2;
-            const uint64_t X = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, rect_slots(I, a, l, cc, d), k);
+            const uint64_t X = hyp<PAR, TERMS>(make_stream(I.seed, code, 0, TAG_UTREE), Nn, rect_slots(I, a, l, cc, d), k);
             if (ci < l) { b = l; k = X; code = 4 * code; }
             else        { a = l; k = k - X; code = 4 * code + 1; }
             continue;
         }
         if (b - a == 1) {
             const uint64_t q = cc + (d - cc + 1) / 2;
-            const uint64_t X = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, rect_slots(I, a, b, cc, q), k);
+            const uint64_t X = hyp<PAR, TERMS>(make_stream(I.seed, code, 0, TAG_UTREE), Nn, rect_slots(I, a, b, cc, q), k);
             if (cj < q) { d = q; k = X; code = 4 * code; }
             else        { cc = q; k = k - X; code = 4 * code + 1; }
             continue;
@@ -612,10 +685,10 @@ __device__ __forceinline__ uint64_t utree_count(const Inst &I, uint64_t ci, uint
         const uint64_t N00 = rect_slots(I, a, l, cc, q), N01 = rect_slots(I, a, l, q, d);
         const uint64_t N10 = rect_slots(I, l, b, cc, q);
         const uint32_t quad = (ci >= l ? 2u : 0u) + (cj >= q ? 1u : 0u);
-        const uint64_t X00 = hyp(make_stream(I.seed, code, 0, TAG_UTREE), Nn, N00, k);
+        const uint64_t X00 = hyp<PAR, TERMS>(make_stream(I.seed, code, 0, TAG_UTREE), Nn, N00, k);
         uint64_t X01 = 0, X10 = 0;
-        if (quad >= 1) X01 = hyp(make_stream(I.seed, code, 1, TAG_UTREE), Nn - N00, N01, k - X00);
-        if (quad >= 2) X10 = hyp(make_stream(I.seed, code, 2, TAG_UTREE), Nn - N00 - N01, N10, k - X00 - X01);
+        if (quad >= 1) X01 = hyp<PAR, TERMS>(make_stream(I.seed, code, 1, TAG_UTREE), Nn - N00, N01, k - X00);
+        if (quad >= 2) X10 = hyp<PAR, TERMS>(make_stream(I.seed, code, 2, TAG_UTREE), Nn - N00 - N01, N10, k - X00 - X01);
         const uint64_t kk = quad == 0 ? X00 : quad == 1 ? X01 : quad == 2 ? X10 : k - X00 - X01 - X10;
         if (quad < 2) b = l; else a = l;
         if (quad & 1) cc = q; else d = q;

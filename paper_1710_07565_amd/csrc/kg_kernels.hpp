@@ -93,13 +93,25 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v)
 }
 
 // ---------------------------------------------------------------------------
-// count: one lane per chunk (a wave per 64 chunks).  Writes the chunk's edge
-// count, tile count and planner-unit count, and the wave's three sums to
-// bsum (the first phase of the offset scan).
+// count: a group of PAR * TERMS lanes per chunk, a workgroup per 64 chunks.
+// The count of a chunk is a root path of dependent variates (Sec. 4.1, 4.2)
+// or one binomial (Sec. 4.3), so the kernel's time is the latency of that
+// chain: the lanes of a chunk try PAR ratio-of-uniforms proposals of each
+// variate at once and, with TERMS = 4, form each proposal's log-factorial
+// differences in four lanes (the first accepted proposal in proposal order
+// wins, so the counts are those of the one-proposal loop).  Writes the
+// chunk's edge count, tile count and planner-unit count, and the workgroup's
+// three sums to bsum (the first phase of the offset scan).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void count_kernel(Job job)
+template <int PAR, int TERMS>
+__global__ __launch_bounds__(64 * PAR * TERMS) void count_kernel(Job job)
 {
-    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x;
+    constexpr int kCountPar = PAR, kCountTerms = TERMS;
+    constexpr int kCountLanes = PAR * TERMS, kCountWaves = PAR * TERMS;   // 64 chunks per workgroup
+    __shared__ uint64_t s_sum[kCountWaves][3];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t g = (uint64_t)blockIdx.x * 64 + threadIdx.x / kCountLanes;
+    const bool lead = (threadIdx.x & (kCountLanes - 1)) == 0;
     uint64_t cnt = 0, T = 0, Us = 0;
     if (g < job.G) {
         const uint32_t i = inst_of_chunk(job, g);
@@ -107,29 +119,40 @@ __global__ __launch_bounds__(64) void count_kernel(Job job)
         const uint64_t c = chunk_ordinal(I, g - I.chunk_base);
         const Chunk ch = chunk_geometry(I, c);
         if (I.model == 1) {
-            cnt = binom(make_stream(I.seed, (uint32_t)c, 0, TAG_CBIN), ch.N, I.p);
+            cnt = binom<kCountPar, kCountTerms>(make_stream(I.seed, (uint32_t)c, 0, TAG_CBIN), ch.N, I.p);
         } else if (I.directed) {
-            cnt = dtree_count(I, c);
+            cnt = dtree_count<kCountPar, kCountTerms>(I, c);
         } else {
             uint64_t lo = 0, hi = I.P;
             while (hi - lo > 1) {
                 const uint64_t mid = (lo + hi) >> 1;
                 if (uord(I.P, mid) <= c) lo = mid; else hi = mid;
             }
-            cnt = utree_count(I, lo, lo + (c - uord(I.P, lo)));
+            cnt = utree_count<kCountPar, kCountTerms>(I, lo, lo + (c - uord(I.P, lo)));
         }
         T = tiles_of(ch.N, I.s);
         Us = T ? (1ull << unit_depth(T, job.unit_log)) : 0;
-        job.off[g] = cnt;
-        job.tstart[g] = T;
-        job.ustart[g] = Us;
+        if (lead) {
+            job.off[g] = cnt;
+            job.tstart[g] = T;
+            job.ustart[g] = Us;
+        }
     }
+    if (!lead) cnt = T = Us = 0;
     const uint64_t sc = wave_incl_scan64(cnt), st = wave_incl_scan64(T), su = wave_incl_scan64(Us);
-    if (threadIdx.x == 63) {
+    if (lane == 63) {
+        s_sum[wv][0] = sc;
+        s_sum[wv][1] = st;
+        s_sum[wv][2] = su;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const uint32_t a = threadIdx.x;
+        uint64_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kCountWaves; ++w) t += s_sum[w][a];
         const uint64_t nb = (job.G + 63) / 64;
-        job.bsum[blockIdx.x] = sc;
-        job.bsum[nb + blockIdx.x] = st;
-        job.bsum[2 * nb + blockIdx.x] = su;
+        job.bsum[a * nb + blockIdx.x] = t;
     }
 }
 

@@ -41,6 +41,21 @@ constexpr uint64_t kMaxChunks = 1ull << 36;   // chunks of one call (a batch: al
 int64_t g_leaf_cap = 0;        // 0: default
 int64_t g_sample_waves = 0;    // per CU
 int64_t g_plan_waves = 0;      // per CU
+int64_t g_count_lanes = 0;     // lanes per chunk in the count kernel (0: chosen per call)
+
+// The HIP error behind the most recent KG_EDEVICE from a launch on this
+// thread (kg_last_hip_error).
+thread_local int t_last_hip_error = 0;
+
+// Whether the launches since the last check were accepted; a failure's
+// HIP error code is kept for kg_last_hip_error.
+bool launched_ok()
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return true;
+    t_last_hip_error = (int)e;
+    return false;
+}
 int64_t g_time_kernels = 0;
 
 // Event pairs recorded around kernel launches while timing is on.
@@ -123,6 +138,7 @@ kg_status capture_check(hipStream_t s, const void *d_ws)
 
 int g_sample_blocks_per_cu[64];
 int g_plan_blocks_per_cu[64];
+int g_count_blocks_per_cu[64][3];   // count kernel with 1, 4, 8 lanes per chunk
 
 kg_status ensure_init(int *dev_out)
 {
@@ -142,12 +158,22 @@ kg_status ensure_init(int *dev_out)
     nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_plan_blocks_per_cu[dev] = nb;
+    {
+        const void *fk[3] = {(const void *)count_kernel<1, 1>, (const void *)count_kernel<1, 4>,
+                             (const void *)count_kernel<2, 4>};
+        const int threads[3] = {64, 256, 512};
+        for (int v = 0; v < 3; ++v) {
+            nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk[v], threads[v], 0) != hipSuccess || nb < 0) nb = 0;
+            g_count_blocks_per_cu[dev][v] = nb;
+        }
+    }
     // this device's copy of the static scratch (its own address per device)
     void *sp = nullptr;
     if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return KG_EDEVICE;
     g_scratch_ptr[dev] = sp;
     hipLaunchKernelGGL(lnf_init_kernel, dim3(1), dim3(64), 0, 0);
-    if (hipGetLastError() != hipSuccess) return KG_EDEVICE;
+    if (!launched_ok()) return KG_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return KG_EDEVICE;
     g_init_done[dev] = true;
     return KG_OK;
@@ -340,9 +366,29 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
     return job;
 }
 
+// The count kernel's lanes per chunk: its time is the latency of each
+// chunk's chain of variates, so a chunk gets as many lanes (8, then 4) as
+// keep every workgroup of the launch resident at once; a launch too large
+// for that takes one lane per chunk (the least work per variate).  Launch
+// shape only: the counts are the same for every choice.
+void launch_count(const Job &job, uint64_t nb, int dev, hipStream_t s)
+{
+    int v = 0;
+    if (g_count_lanes) {
+        v = g_count_lanes == 8 ? 2 : g_count_lanes == 4 ? 1 : 0;
+    } else {
+        const uint64_t cu = (uint64_t)g_num_cu[dev];
+        for (int c = 2; c >= 1; --c)
+            if (nb <= cu * (uint64_t)g_count_blocks_per_cu[dev][c]) { v = c; break; }
+    }
+    if (v == 2) hipLaunchKernelGGL((count_kernel<2, 4>), dim3((uint32_t)nb), dim3(512), 0, s, job);
+    else if (v == 1) hipLaunchKernelGGL((count_kernel<1, 4>), dim3((uint32_t)nb), dim3(256), 0, s, job);
+    else hipLaunchKernelGGL((count_kernel<1, 1>), dim3((uint32_t)nb), dim3(64), 0, s, job);
+}
+
 // count + scan (+ instance offsets).  `resident`: the descriptor table is
 // already in the workspace (kg_batch_upload).
-kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s, bool resident)
+kg_status launch_counts(const Prepared &P, Job &job, int dev, hipStream_t s, bool resident)
 {
     if (job.ninst > 1 && !resident) {
         if (hipMemcpyAsync((void *)job.insts, P.insts.data(), P.insts.size() * sizeof(Inst),
@@ -352,7 +398,7 @@ kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s, bool residen
     const uint64_t nb = (P.G + 63) / 64;
     {
         KernelTimer tm(KG_KERNEL_COUNT, s);
-        hipLaunchKernelGGL(count_kernel, dim3((uint32_t)nb), dim3(64), 0, s, job);
+        launch_count(job, nb, dev, s);
     }
     {
         KernelTimer tm(KG_KERNEL_SCAN, s);
@@ -361,7 +407,7 @@ kg_status launch_counts(const Prepared &P, Job &job, hipStream_t s, bool residen
     }
     if (job.inst_off)
         hipLaunchKernelGGL(inst_offsets_kernel, dim3((job.ninst + 1 + 255) / 256), dim3(256), 0, s, job);
-    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+    return launched_ok() ? KG_OK : KG_EDEVICE;
 }
 
 kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
@@ -389,7 +435,7 @@ kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
         KernelTimer tm(KG_KERNEL_QUEUE, s);
         hipLaunchKernelGGL(queue_kernel<kCapMax>, dim3((uint32_t)qgrid), dim3(64), 0, s, job);
     }
-    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+    return launched_ok() ? KG_OK : KG_EDEVICE;
 }
 
 kg_status run(const kg_instance *inst, uint32_t count, uint32_t *edges, uint64_t capacity,
@@ -418,14 +464,14 @@ kg_status run(const kg_instance *inst, uint32_t count, uint32_t *edges, uint64_t
     if (d_counts) {
         // counts only: run the count kernel and copy the per-chunk counts out
         const uint64_t nb = (P.G + 63) / 64;
-        hipLaunchKernelGGL(count_kernel, dim3((uint32_t)nb), dim3(64), 0, s, job);
-        if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+        launch_count(job, nb, dev, s);
+        if (!launched_ok()) st = KG_EDEVICE;
         else if (hipMemcpyAsync(d_counts, job.off, P.G * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
             st = KG_EDEVICE;
         release(ws, s);
         return st;
     }
-    st = launch_counts(P, job, s, resident);
+    st = launch_counts(P, job, dev, s, resident);
     if (!st && counts_only) {
         uint64_t tot = 0;
         if (hipMemcpyAsync(&tot, job.status, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -706,7 +752,7 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
     // kernels; their binomial total is not this sampler's, so no capacity
     // check and no total there
     Job job = make_job(P, ws, d_edges, ~0ull);
-    st = launch_counts(P, job, s, false);
+    st = launch_counts(P, job, dev, s, false);
     if (!st) {
         {
             KernelTimer tm(KG_KERNEL_PLAN, s);
@@ -720,7 +766,7 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
             KernelTimer tm(KG_KERNEL_SAMPLE, s);
             hipLaunchKernelGGL(skip_write_kernel, dim3((uint32_t)nw), dim3(64), 0, s, jw);
         }
-        if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+        if (!launched_ok()) st = KG_EDEVICE;
     }
     release(ws, s);
     return st;
@@ -806,7 +852,7 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
         KernelTimer tm(KG_KERNEL_SAMPLE, s);
         hipLaunchKernelGGL(rgg_edges_kernel<true>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
     }
-    if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+    if (!launched_ok()) st = KG_EDEVICE;
     release(ws, s);
     return st;
 }
@@ -891,7 +937,7 @@ kg_status kg_rgg3d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
         KernelTimer tm(KG_KERNEL_SAMPLE, s);
         hipLaunchKernelGGL(rgg3_edges_kernel<true>, dim3((uint32_t)nwg), dim3(64), 0, s, J);
     }
-    if (hipGetLastError() != hipSuccess) st = KG_EDEVICE;
+    if (!launched_ok()) st = KG_EDEVICE;
     release(ws, s);
     return st;
 }
@@ -939,7 +985,7 @@ kg_status kg_edge_hash(const uint32_t *d_edges, uint64_t n_edges, uint64_t *d_ha
     if (grid < 1) grid = 1;
     if (grid > 2048) grid = 2048;
     hipLaunchKernelGGL(hash_kernel, dim3((uint32_t)grid), dim3(256), 0, s, d_edges, n_edges, d_hash);
-    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+    return launched_ok() ? KG_OK : KG_EDEVICE;
 }
 
 kg_status kg_set_workspace(void *d_workspace, uint64_t workspace_bytes)
@@ -979,6 +1025,10 @@ kg_status kg_set_option(int option, int64_t value)
     case KG_OPT_TIME_KERNELS:
         if (value > 1) return KG_ERANGE;
         g_time_kernels = value;
+        return KG_OK;
+    case KG_OPT_COUNT_LANES:
+        if (value != 0 && value != 1 && value != 4 && value != 8) return KG_ERANGE;
+        g_count_lanes = value;
         return KG_OK;
     default:
         return KG_EINVAL;
@@ -1021,7 +1071,12 @@ kg_status kg_eval(int fn, const void *d_in, void *d_out, uint64_t n, void *strea
     const uint64_t nb = (n + 255) / 256;
     if (nb > 0x7FFFFFFFull) return KG_ERANGE;
     hipLaunchKernelGGL(eval_kernel, dim3((uint32_t)nb), dim3(256), 0, (hipStream_t)stream, fn, d_in, d_out, n);
-    return hipGetLastError() == hipSuccess ? KG_OK : KG_EDEVICE;
+    return launched_ok() ? KG_OK : KG_EDEVICE;
+}
+
+int kg_last_hip_error(void)
+{
+    return t_last_hip_error;
 }
 
 int64_t kg_get_option(int option)
@@ -1031,6 +1086,7 @@ int64_t kg_get_option(int option)
     case KG_OPT_SAMPLE_WAVES: return g_sample_waves;     // 0: as many as fit on a compute unit
     case KG_OPT_PLAN_WAVES: return g_plan_waves;
     case KG_OPT_TIME_KERNELS: return g_time_kernels;
+    case KG_OPT_COUNT_LANES: return g_count_lanes;
     default: return -1;
     }
 }

@@ -35,6 +35,14 @@ def test_every_declared_symbol_is_exported(L):
         assert hasattr(L, n), n
 
 
+def test_one_hip_runtime_in_the_process(L):
+    """The binding loads libkg.so after torch, so the library binds to the HIP
+    runtime torch holds instead of loading the system copy beside it."""
+    maps = open("/proc/self/maps").read().split("\n")
+    runtimes = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(runtimes) == 1, runtimes
+
+
 def test_library_is_built_for_gfx950():
     from paper_1710_07565_amd import _lib
     data = open(_lib.LIB_PATH, "rb").read()
@@ -116,6 +124,9 @@ def test_generation_calls_reject_bad_arguments_without_a_device(L):
     assert L.kg_set_option(42, 1) == _lib.KG_EINVAL
     assert L.kg_set_option(2, 8) == 0 and L.kg_get_option(2) == 8
     assert L.kg_set_option(2, 0) == 0 and L.kg_get_option(2) == 0
+    assert L.kg_set_option(_lib.KG_OPT_COUNT_LANES, 3) == _lib.KG_ERANGE
+    assert L.kg_set_option(_lib.KG_OPT_COUNT_LANES, 8) == 0 and L.kg_get_option(_lib.KG_OPT_COUNT_LANES) == 8
+    assert L.kg_set_option(_lib.KG_OPT_COUNT_LANES, 0) == 0 and L.kg_get_option(_lib.KG_OPT_COUNT_LANES) == 0
 
 
 def test_oracle_tile_exponent_is_minimal(kgref):

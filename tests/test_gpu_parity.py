@@ -145,10 +145,17 @@ def test_chunk_counts(kg, kgref, n, directed, P, model):
         p = (16.0 if directed else 64.0) / (n - 1)
         inst = kg.Instance(n, kg.GNP, directed, 0, p, 1, P)
         ref = kgref.inst(n, p=p, directed=directed, seed=1, chunks=P, model=1)
-    got = to_np_u64(kg.chunk_counts(inst))
-    torch.cuda.synchronize()
     want = kgref.chunk_counts(ref)
-    assert np.array_equal(got, want)
+    # the count kernel's lanes per chunk (launch shape only): automatic, then
+    # each fixed choice
+    try:
+        for lanes in (0, 1, 4, 8):
+            kg.set_option(kg._lib.KG_OPT_COUNT_LANES, lanes)
+            got = to_np_u64(kg.chunk_counts(inst))
+            torch.cuda.synchronize()
+            assert np.array_equal(got, want), "lanes per chunk %d" % lanes
+    finally:
+        kg.set_option(kg._lib.KG_OPT_COUNT_LANES, 0)
 
 
 def test_gnp_count_and_overflow(kg, kgref):
