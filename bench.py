@@ -811,7 +811,7 @@ def main():
                     help="no run: read rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of a profiled "
                          "run of this workload (with --calibrate-copy-gib) and record the tile_kernel HBM traffic "
                          "in profiles/tile_kernel_traffic.json")
-    ap.add_argument("--count-lanes", type=int, default=0, choices=[0, 1, 4, 8],
+    ap.add_argument("--count-lanes", type=int, default=0, choices=[0, 1, 2, 4, 8],
                     help="lanes per chunk in the count kernel (0: the library's choice; launch shape only)")
     ap.add_argument("--traffic-command", action="append", default=[],
                     help="the profiling commands, recorded with the traffic figure")

@@ -278,7 +278,7 @@ enum {
     KG_OPT_SAMPLE_WAVES = 2,    /* resident sampler waves per compute unit (1..32) */
     KG_OPT_PLAN_WAVES = 3,      /* resident tile-planner waves per compute unit (1..64) */
     KG_OPT_TIME_KERNELS = 4,    /* 1: bracket every kernel launch with hipEvents (not under capture) */
-    KG_OPT_COUNT_LANES = 5      /* lanes per chunk in the count kernel (1, 4 or 8; 0: the most for
+    KG_OPT_COUNT_LANES = 5      /* lanes per chunk in the count kernel (1, 2, 4 or 8; 0: the most for
                                    which every workgroup of the launch is resident at once) */
 };
 kg_status kg_set_option(int option, int64_t value);

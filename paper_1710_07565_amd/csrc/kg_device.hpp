@@ -314,23 +314,26 @@ struct BinRatio {
     }
 };
 
-// Quad broadcast: the value of lane T of each group of four lanes, to all
-// four (DPP quad_perm; the four lanes are active together).
-template <int T>
-__device__ __forceinline__ double quad_bcast(double v)
+// Broadcast within aligned lane groups of G = 2 or 4 lanes: the value of lane
+// T of each group, to the whole group (DPP quad_perm; the group's lanes are
+// active together).
+template <int G, int T>
+__device__ __forceinline__ double group_bcast(double v)
 {
+    static_assert((G == 2 && T < 2) || (G == 4 && T < 4), "lane within a group of 2 or 4");
+    constexpr int ctrl = G == 4 ? T * 0x55 : (T | T << 2 | (T + 2) << 4 | (T + 2) << 6);
     const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, T * 0x55, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), T * 0x55, 0xF, 0xF, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, ctrl, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), ctrl, 0xF, 0xF, false);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // PAR = 1, TERMS = 1: one proposal at a time in one lane.  Otherwise an
 // aligned group of PAR * TERMS lanes works on one variate (the same
 // arguments in every lane of the group): it tries proposals j0 .. j0 + PAR - 1
-// at once, and with TERMS = 4 the four log-factorial differences of a
-// proposal's ratio are formed in the four lanes of a quad and summed in the
-// sequential order.  The lowest accepted proposal wins, so the variate is
+// at once, and with TERMS = 2 or 4 the four log-factorial differences of a
+// proposal's ratio are spread over TERMS lanes (lane t forms differences t,
+// t + TERMS, ...) and summed in the sequential order.  The lowest accepted proposal wins, so the variate is
 // the one the sequential loop returns.  Used where a variate's latency, not
 // the lanes' throughput, bounds a kernel.
 template <int PAR, int TERMS, class Ratio>
@@ -338,7 +341,7 @@ __device__ __forceinline__ uint64_t rou_sample(const Stream &s, double a, double
                                                const Ratio &ratio)
 {
     static_assert(PAR == 1 || PAR == 2 || PAR == 4 || PAR == 8, "1, 2, 4 or 8 proposals at once");
-    static_assert(TERMS == 1 || TERMS == 4, "ratio in one lane or in a quad");
+    static_assert(TERMS == 1 || TERMS == 2 || TERMS == 4, "ratio in one, two or four lanes");
     constexpr uint32_t GL = PAR * TERMS;     // lanes per variate
     const double upper_excl = (double)upper + 1.0;
     const uint32_t lane = __lane_id();
@@ -357,9 +360,14 @@ __device__ __forceinline__ uint64_t rou_sample(const Stream &s, double a, double
                 double T;
                 if (TERMS == 1) {
                     T = ratio(X);
+                } else if (TERMS == 2) {
+                    const double da = ratio.term(tq, X), db = ratio.term(tq + 2, X);
+                    T = ratio.combine(group_bcast<2, 0>(da), group_bcast<2, 1>(da), group_bcast<2, 0>(db),
+                                      group_bcast<2, 1>(db), X);
                 } else {
                     const double d = ratio.term(tq, X);
-                    T = ratio.combine(quad_bcast<0>(d), quad_bcast<1>(d), quad_bcast<2>(d), quad_bcast<3>(d), X);
+                    T = ratio.combine(group_bcast<4, 0>(d), group_bcast<4, 1>(d), group_bcast<4, 2>(d),
+                                      group_bcast<4, 3>(d), X);
                 }
                 if (U * (4.0 - U) - 3.0 <= T) acc = true;
                 else if (U * (U - T) >= 1.0) acc = false;
@@ -463,7 +471,10 @@ struct HypRun {
         }
     }
 
-    // one proposal; true once the variate is known
+    // one proposal; true once the variate is known.  TERMS = 2 or 4: the
+    // aligned group of TERMS lanes holding the same state forms the ratio's
+    // four differences together (same value in every lane of the group).
+    template <int TERMS = 1>
     __device__ __forceinline__ bool step()
     {
         if (done) return true;
@@ -474,7 +485,20 @@ struct HypRun {
         if (!(t >= 0.0) || t >= upper_excl) return false;
         const uint64_t X = (uint64_t)floor(t);
         if (X > lo) return false;
-        const double T = HypRatio{N, hi, lo, M}(X);
+        const HypRatio ratio{N, hi, lo, M};
+        double T;
+        if (TERMS == 1) {
+            T = ratio(X);
+        } else if (TERMS == 2) {
+            const uint32_t tq = __lane_id() & 1;
+            const double da = ratio.term(tq, X), db = ratio.term(tq + 2, X);
+            T = ratio.combine(group_bcast<2, 0>(da), group_bcast<2, 1>(da), group_bcast<2, 0>(db),
+                              group_bcast<2, 1>(db), X);
+        } else {
+            const double d = ratio.term(__lane_id() & 3, X);
+            T = ratio.combine(group_bcast<4, 0>(d), group_bcast<4, 1>(d), group_bcast<4, 2>(d),
+                              group_bcast<4, 3>(d), X);
+        }
         bool acc = false;
         if (U * (4.0 - U) - 3.0 <= T) acc = true;
         else if (U * (U - T) >= 1.0) acc = false;

@@ -263,10 +263,15 @@ __global__ __launch_bounds__(256) void inst_offsets_kernel(Job job)
 // counts left of it), then traverses the unit depth first, left child first,
 // so leaves come in tile order and each tile's output offset is a running
 // sum.  Every split is one HypRun, advanced by one proposal per loop trip;
-// pending right children wait on a small per-lane stack in LDS.
+// pending right children wait on a small per-lane stack in LDS.  With
+// TERMS = 2 or 4 a unit belongs to a group of that many lanes, which keep
+// the same state and spread each proposal's four log-factorial differences
+// over the group (for launches with few units, where one unit's chain of
+// variates, not the lanes' throughput, sets the time).
 // ---------------------------------------------------------------------------
 constexpr int kPlanStack = 8;   // > depth of a unit subtree (6 for 64 tiles)
 
+template <int TERMS>
 __global__ __launch_bounds__(64) void plan_kernel(Job job)
 {
     __shared__ uint64_t st_k[kPlanStack][64];
@@ -274,11 +279,11 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
     const uint32_t lane = threadIdx.x;
     if (job.status[1]) return;
     const uint64_t U = job.status[3];
-    // blocked unit ranges: a lane's next unit is the following one, so the
-    // chunk index only moves forward (one binary search per lane)
-    const uint64_t TL = (uint64_t)gridDim.x * 64;
+    // blocked unit ranges: a lane group's next unit is the following one, so
+    // the chunk index only moves forward (one binary search per group)
+    const uint64_t TL = (uint64_t)gridDim.x * (64 / TERMS);
     const uint64_t per = (U + TL - 1) / TL;
-    uint64_t u = ((uint64_t)blockIdx.x * 64 + lane) * per;
+    uint64_t u = ((uint64_t)blockIdx.x * 64 + lane) / TERMS * per;
     const uint64_t uend = u + per < U ? u + per : U;
     bool active = u < uend;
     uint64_t g = 0;
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(64) void plan_kernel(Job job)
                     running = true;
                 }
             }
-            if (active && running && hr.step()) {
+            if (active && running && hr.template step<TERMS>()) {
                 const uint64_t X = hr.result();
                 const uint64_t mid = lo + (hi - lo + 1) / 2;
                 running = false;

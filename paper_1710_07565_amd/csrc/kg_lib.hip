@@ -138,7 +138,9 @@ kg_status capture_check(hipStream_t s, const void *d_ws)
 
 int g_sample_blocks_per_cu[64];
 int g_plan_blocks_per_cu[64];
-int g_count_blocks_per_cu[64][3];   // count kernel with 1, 4, 8 lanes per chunk
+int g_skip_blocks_per_cu[64];
+constexpr int kCountVariants = 4;   // count kernel with 1, 2, 4, 8 lanes per chunk
+int g_count_blocks_per_cu[64][kCountVariants];
 
 kg_status ensure_init(int *dev_out)
 {
@@ -156,13 +158,16 @@ kg_status ensure_init(int *dev_out)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_sample_blocks_per_cu[dev] = nb;
     nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_kernel<1>, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_plan_blocks_per_cu[dev] = nb;
+    nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, skip_write_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    g_skip_blocks_per_cu[dev] = nb;
     {
-        const void *fk[3] = {(const void *)count_kernel<1, 1>, (const void *)count_kernel<1, 4>,
-                             (const void *)count_kernel<2, 4>};
-        const int threads[3] = {64, 256, 512};
-        for (int v = 0; v < 3; ++v) {
+        const void *fk[kCountVariants] = {(const void *)count_kernel<1, 1>, (const void *)count_kernel<1, 2>,
+                                          (const void *)count_kernel<1, 4>, (const void *)count_kernel<2, 4>};
+        const int threads[kCountVariants] = {64, 128, 256, 512};
+        for (int v = 0; v < kCountVariants; ++v) {
             nb = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk[v], threads[v], 0) != hipSuccess || nb < 0) nb = 0;
             g_count_blocks_per_cu[dev][v] = nb;
@@ -367,7 +372,7 @@ Job make_job(const Prepared &P, const Workspace &ws, uint32_t *edges, uint64_t c
 }
 
 // The count kernel's lanes per chunk: its time is the latency of each
-// chunk's chain of variates, so a chunk gets as many lanes (8, then 4) as
+// chunk's chain of variates, so a chunk gets as many lanes (8, 4, then 2) as
 // keep every workgroup of the launch resident at once; a launch too large
 // for that takes one lane per chunk (the least work per variate).  Launch
 // shape only: the counts are the same for every choice.
@@ -375,14 +380,15 @@ void launch_count(const Job &job, uint64_t nb, int dev, hipStream_t s)
 {
     int v = 0;
     if (g_count_lanes) {
-        v = g_count_lanes == 8 ? 2 : g_count_lanes == 4 ? 1 : 0;
+        v = g_count_lanes == 8 ? 3 : g_count_lanes == 4 ? 2 : g_count_lanes == 2 ? 1 : 0;
     } else {
         const uint64_t cu = (uint64_t)g_num_cu[dev];
-        for (int c = 2; c >= 1; --c)
+        for (int c = kCountVariants - 1; c >= 1; --c)
             if (nb <= cu * (uint64_t)g_count_blocks_per_cu[dev][c]) { v = c; break; }
     }
-    if (v == 2) hipLaunchKernelGGL((count_kernel<2, 4>), dim3((uint32_t)nb), dim3(512), 0, s, job);
-    else if (v == 1) hipLaunchKernelGGL((count_kernel<1, 4>), dim3((uint32_t)nb), dim3(256), 0, s, job);
+    if (v == 3) hipLaunchKernelGGL((count_kernel<2, 4>), dim3((uint32_t)nb), dim3(512), 0, s, job);
+    else if (v == 2) hipLaunchKernelGGL((count_kernel<1, 4>), dim3((uint32_t)nb), dim3(256), 0, s, job);
+    else if (v == 1) hipLaunchKernelGGL((count_kernel<1, 2>), dim3((uint32_t)nb), dim3(128), 0, s, job);
     else hipLaunchKernelGGL((count_kernel<1, 1>), dim3((uint32_t)nb), dim3(64), 0, s, job);
 }
 
@@ -416,10 +422,15 @@ kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
     // planner units: at most 2 per 2^unit_log tiles plus one per chunk; one lane each
     const uint64_t ub = 2 * (P.Tb >> job.unit_log) + P.G + 1;
     uint64_t pgrid = (uint64_t)(cu * opt_or(g_plan_waves, g_plan_blocks_per_cu[dev]));
-    if (pgrid > (ub + 63) / 64) pgrid = (ub + 63) / 64;
+    // few units (their bound fits the resident lanes 4 or 2 times over): a
+    // group of lanes per unit shortens each unit's chain of variates
+    const int terms = ub * 4 <= pgrid * 64 ? 4 : ub * 2 <= pgrid * 64 ? 2 : 1;
+    if (pgrid > (ub * terms + 63) / 64) pgrid = (ub * terms + 63) / 64;
     {
         KernelTimer tm(KG_KERNEL_PLAN, s);
-        hipLaunchKernelGGL(plan_kernel, dim3((uint32_t)pgrid), dim3(64), 0, s, job);
+        if (terms == 4) hipLaunchKernelGGL(plan_kernel<4>, dim3((uint32_t)pgrid), dim3(64), 0, s, job);
+        else if (terms == 2) hipLaunchKernelGGL(plan_kernel<2>, dim3((uint32_t)pgrid), dim3(64), 0, s, job);
+        else hipLaunchKernelGGL(plan_kernel<1>, dim3((uint32_t)pgrid), dim3(64), 0, s, job);
     }
     uint64_t sgrid = (uint64_t)(cu * opt_or(g_sample_waves, g_sample_blocks_per_cu[dev]));
     if (sgrid > P.Tb + 1) sgrid = P.Tb + 1;
@@ -762,9 +773,12 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
         jw.capacity = capacity_edges;
         jw.out_total = d_total;
         hipLaunchKernelGGL(skip_scan_kernel, dim3(1), dim3(1024), 0, s, jw, nw);
+        hipLaunchKernelGGL(skip_fix_kernel, dim3((uint32_t)((P.Tb + 1 + 63) / 64)), dim3(64), 0, s, jw);
         {
             KernelTimer tm(KG_KERNEL_SAMPLE, s);
-            hipLaunchKernelGGL(skip_write_kernel, dim3((uint32_t)nw), dim3(64), 0, s, jw);
+            uint64_t wgrid = (uint64_t)g_num_cu[dev] * (uint64_t)g_skip_blocks_per_cu[dev];
+            if (wgrid > P.Tb + 1) wgrid = P.Tb + 1;
+            hipLaunchKernelGGL(skip_write_kernel, dim3((uint32_t)wgrid), dim3(64), 0, s, jw);
         }
         if (!launched_ok()) st = KG_EDEVICE;
     }
@@ -1027,7 +1041,7 @@ kg_status kg_set_option(int option, int64_t value)
         g_time_kernels = value;
         return KG_OK;
     case KG_OPT_COUNT_LANES:
-        if (value != 0 && value != 1 && value != 4 && value != 8) return KG_ERANGE;
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8) return KG_ERANGE;
         g_count_lanes = value;
         return KG_OK;
     default:

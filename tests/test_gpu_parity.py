@@ -149,7 +149,7 @@ def test_chunk_counts(kg, kgref, n, directed, P, model):
     # the count kernel's lanes per chunk (launch shape only): automatic, then
     # each fixed choice
     try:
-        for lanes in (0, 1, 4, 8):
+        for lanes in (0, 1, 2, 4, 8):
             kg.set_option(kg._lib.KG_OPT_COUNT_LANES, lanes)
             got = to_np_u64(kg.chunk_counts(inst))
             torch.cuda.synchronize()

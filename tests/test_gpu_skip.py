@@ -12,7 +12,12 @@ pytestmark = pytest.mark.gpu
 
 CASES = [(60, 0.05, True, 5), (97, 0.3, False, 7), (40, 0.8, True, 3), (50, 1.0, False, 4), (90, 0.0, True, 3),
          (2**12, 16 / (2**12 - 1), True, 64), (5000, 0.01, False, 7), (3000, 0.9, True, 2), (1, 0.5, True, 1),
-         (2**16, 1e-5, True, 256), (20000, 2e-4, False, 200)]
+         (2**16, 1e-5, True, 256), (20000, 2e-4, False, 200),
+         # about 1440 successes per 4096-slot tile: most tiles fill the write
+         # pass's LDS batch (1408 events) and are stored in two parts
+         (5000, 0.3516, True, 3), (3000, 0.3516, False, 5),
+         # failures just under the batch size when p is just above 1/2
+         (4000, 0.5001, True, 2)]
 
 
 @pytest.mark.parametrize("n,p,directed,P", CASES)
