@@ -1,7 +1,7 @@
 """MI355X generator for Erdos-Renyi graphs G(n,m) / G(n,p), directed or
 undirected, by the communication-free method of Funke et al. (arXiv
-1710.07565, Sec. 4), and for two-dimensional random geometric graphs by the
-same paper's cell method (Sec. 5).
+1710.07565, Sec. 4), and for random geometric graphs in two and three
+dimensions by the same paper's cell method (Sec. 5).
 
 The Python layer only marshals arguments: device memory and streams come
 from PyTorch, every step of the generator runs in the HIP library
