@@ -19,10 +19,10 @@
  *     (Sec. 2.2, Sec. 4.1, Sec. 4.2 quadrant recursion, split l = ceil(P/2)).
  *   - G(n,p) chunk counts are binomial, keyed by the chunk id (Sec. 4.3).
  *   - Below a threshold a sequential sampler draws the chunk's sample
- *     (Sec. 2.2); our threshold is a tile of 2^s slots holding 724..1448
- *     expected samples (1024 within a factor sqrt 2), itself split by a
- *     hypergeometric tree, and the base case draws until k distinct slots
- *     are seen.
+ *     (Sec. 2.2); our threshold is a tile of 2^s slots holding 560..1120
+ *     expected samples (1024 whenever the density is a power of two),
+ *     itself split by a hypergeometric tree, and the base case draws until
+ *     k distinct slots are seen.
  *   - Variates by acceptance-rejection (Sec. 2.2): discrete ratio of
  *     uniforms for the hypergeometric and binomial laws, direct simulation
  *     for small hypergeometric samples, geometric waiting times for
@@ -425,7 +425,7 @@ typedef struct {
 
 enum { KGREF_OK = 0, KGREF_EINVAL = -1, KGREF_ERANGE = -2, KGREF_ENOSPC = -3 };
 
-#define LAMBDA 724u   /* expected samples per tile in [724, 1448): about 1024 / sqrt 2 .. 1024 sqrt 2 */
+#define LAMBDA 560u   /* expected samples per tile in [560, 1120); 1024 when the density is a power of two */
 
 static uint64_t slots_total(const kgref_inst *I)
 {

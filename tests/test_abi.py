@@ -130,14 +130,14 @@ def test_generation_calls_reject_bad_arguments_without_a_device(L):
 
 
 def test_oracle_tile_exponent_is_minimal(kgref):
-    """The tile exponent is the smallest s in [9, 32] with 2^s m >= 724 N
-    (tiles hold 724..1448 samples in expectation)."""
+    """The tile exponent is the smallest s in [9, 32] with 2^s m >= 560 N
+    (tiles hold 560..1120 samples in expectation)."""
     for n, m in [(2**16, 2**20), (2**10, 2**19), (50, 1225), (2**20, 5)]:
         I = kgref.inst(n, m=m, directed=True, seed=1, chunks=1)
         s = kgref.tile_exponent(I)
         N = n * (n - 1)
-        assert (m << s) >= 724 * N or s == 32
-        assert s == 9 or (m << (s - 1)) < 724 * N
+        assert (m << s) >= 560 * N or s == 32
+        assert s == 9 or (m << (s - 1)) < 560 * N
 
 
 def test_skip_variant_argument_checks(L):
@@ -220,7 +220,7 @@ def test_set_workspace_argument_checks(L):
 def test_tile_exponent_of_the_workloads(kgref, n, m, p, directed, P, s_want):
     """The tile exponent of each benchmark workload, checked against the
     sampling threshold's definition written out here: the expected samples
-    of a full tile, 2^s m / N (G(n,m)) or 2^s p (G(n,p)), reach 724 at s and
+    of a full tile, 2^s m / N (G(n,m)) or 2^s p (G(n,p)), reach 560 at s and
     not at s - 1; every one of these workloads lands within 0.02 of 1024."""
     from fractions import Fraction
     model = 0 if p == 0.0 else 1
@@ -229,5 +229,5 @@ def test_tile_exponent_of_the_workloads(kgref, n, m, p, directed, P, s_want):
     assert s == s_want
     N = n * (n - 1) // (1 if directed else 2)
     mean = (lambda t: Fraction(m * 2**t, N)) if model == 0 else (lambda t: Fraction(p) * 2**t)
-    assert mean(s) >= 724 and mean(s - 1) < 724
+    assert mean(s) >= 560 and mean(s - 1) < 560
     assert abs(float(mean(s)) - 1024.0) < 0.02

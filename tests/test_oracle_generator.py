@@ -291,20 +291,20 @@ def test_gnp_geometric_skip_cross_check(kgref):
 
 
 def test_uneven_tile_tree_marginals(kgref):
-    """n=100 directed, m=3000, one chunk: tiles of 2^12 slots -> sizes 4096,
+    """n=100 directed, m=2000, one chunk: tiles of 2^12 slots -> sizes 4096,
     4096, 1708 (the root splits [0,2) | [2,3)).  Each tile count must follow
-    Hyp(9900, size, 3000); a swapped split would move tile 2's mean from
-    517.6 to 1241.2."""
-    I0 = kgref.inst(100, m=3000, directed=True, seed=1, chunks=1)
+    Hyp(9900, size, 2000); a swapped split would move tile 2's mean from
+    345.1 to 827.5."""
+    I0 = kgref.inst(100, m=2000, directed=True, seed=1, chunks=1)
     assert kgref.tile_exponent(I0) == 12
     reps = 3000
     tc = np.zeros((reps, 3), dtype=np.int64)
     for s in range(reps):
-        I = kgref.inst(100, m=3000, directed=True, seed=s, chunks=1)
-        tc[s] = kgref.tile_counts(I, 0, 3000)
-    assert np.all(tc.sum(axis=1) == 3000)
+        I = kgref.inst(100, m=2000, directed=True, seed=s, chunks=1)
+        tc[s] = kgref.tile_counts(I, 0, 2000)
+    assert np.all(tc.sum(axis=1) == 2000)
     for t, size in enumerate([4096, 4096, 1708]):
-        rv = stats.hypergeom(9900, size, 3000)
+        rv = stats.hypergeom(9900, size, 2000)
         assert _degree_chi2(tc[:, t], rv) > 1e-5, t
 
 
