@@ -21,7 +21,7 @@ namespace kg {
 // ---------------------------------------------------------------------------
 // Constants of the method
 // ---------------------------------------------------------------------------
-constexpr uint32_t kLambda = 724;       // tiles hold [724, 1448) samples in expectation (~1024/sqrt 2 .. 1024 sqrt 2)
+constexpr uint32_t kLambda = 560;       // tiles hold [560, 1120) samples in expectation (1024 at power-of-two densities)
 constexpr uint32_t kUnitTiles = 64;     // most tiles of one planner unit (one lane expands it)
 constexpr uint32_t kLnfTab = 1024;      // ln k! tabulated for k <= kLnfTab
 

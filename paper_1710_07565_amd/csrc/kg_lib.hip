@@ -139,6 +139,7 @@ kg_status capture_check(hipStream_t s, const void *d_ws)
 int g_sample_blocks_per_cu[64];
 int g_plan_blocks_per_cu[64];
 int g_skip_blocks_per_cu[64];
+int g_queue_blocks_per_cu[64];
 constexpr int kCountVariants = 4;   // count kernel with 1, 2, 4, 8 lanes per chunk
 int g_count_blocks_per_cu[64][kCountVariants];
 
@@ -163,6 +164,9 @@ kg_status ensure_init(int *dev_out)
     nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, skip_write_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_skip_blocks_per_cu[dev] = nb;
+    nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, queue_kernel<kCapMax>, 64, 0) != hipSuccess || nb < 1) nb = 1;
+    g_queue_blocks_per_cu[dev] = nb;
     {
         const void *fk[kCountVariants] = {(const void *)count_kernel<1, 1>, (const void *)count_kernel<1, 2>,
                                           (const void *)count_kernel<1, 4>, (const void *)count_kernel<2, 4>};
@@ -434,9 +438,11 @@ kg_status launch_generate(const Prepared &P, Job &job, int dev, hipStream_t s)
     }
     uint64_t sgrid = (uint64_t)(cu * opt_or(g_sample_waves, g_sample_blocks_per_cu[dev]));
     if (sgrid > P.Tb + 1) sgrid = P.Tb + 1;
-    // tiles the fast kernel queues are rare; a grid of one wave per compute
-    // unit drains the queue (it exits at once when the queue is empty)
-    uint64_t qgrid = (uint64_t)cu;
+    // the queued tiles (more draws than the register base case holds, or a
+    // bucket too full to sort): rare, the tiles expecting at most 1120
+    // samples; a grid that fills the chip drains them in parallel (every
+    // wave exits at once when the queue is empty)
+    uint64_t qgrid = (uint64_t)(cu * g_queue_blocks_per_cu[dev]);
     if (qgrid > P.Tb + 1) qgrid = P.Tb + 1;
     {
         KernelTimer tm(KG_KERNEL_SAMPLE, s);

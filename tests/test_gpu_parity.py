@@ -98,6 +98,25 @@ def test_small_config_directed(kg, kgref):
     check_equal(got, want, "directed n=2^16 m=2^20 P=64")
 
 
+# Tiles expecting about 1115 samples (the top of the 560..1120 range): the
+# register base case's widest sorts (18 and 20 keys per lane) and its fifth
+# Philox round on most tiles.
+UPPER = [(3000, 1224500, True, 1, 0), (3000, 1224500, True, 7, 0), (2500, 424900, False, 4, 0),
+         (3000, 0.2722, True, 3, 1), (2000, 0.2722, False, 5, 1)]
+
+
+@pytest.mark.parametrize("n,mp,directed,P,model", UPPER)
+def test_tiles_near_the_upper_bound(kg, kgref, n, mp, directed, P, model):
+    if model == 0:
+        got = gpu_gnm(kg, n, mp, directed, 21, P)
+        I = kgref.inst(n, m=mp, directed=directed, seed=21, chunks=P)
+    else:
+        got = gpu_gnp(kg, n, mp, directed, 21, P)
+        I = kgref.inst(n, p=mp, directed=directed, seed=21, chunks=P, model=1)
+    want = kgref.generate(I)
+    check_equal(got, want, "upper n=%d %s dir=%d P=%d" % (n, mp, directed, P))
+
+
 @pytest.mark.parametrize("cap", [128, 200, 512])
 def test_leaf_capacity_does_not_change_bits(kg, kgref, cap):
     """Tiles larger than the LDS pass capacity go through key sub-ranges;
