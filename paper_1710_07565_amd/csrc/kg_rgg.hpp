@@ -116,13 +116,16 @@ __device__ __forceinline__ uint64_t block256_excl_scan(uint64_t v, uint64_t &tot
     return before + incl - v;
 }
 
+// Loads and stores of a tile are lane-strided (item i x 256 + thread), so a
+// wave's access covers 512 contiguous bytes; the apply pass goes through LDS
+// to give each thread its 16 consecutive items.
 __global__ __launch_bounds__(256) void scan_reduce_kernel(const uint64_t *a, uint64_t len, uint64_t *sums)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x;
     uint64_t s = 0;
 #pragma unroll
     for (uint32_t i = 0; i < kScanItems; ++i)
-        if (base + i < len) s += a[base + i];
+        if (base + 256ull * i < len) s += a[base + 256ull * i];
     uint64_t total;
     (void)block256_excl_scan(s, total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
@@ -156,22 +159,36 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t *sums, uint64_
 __global__ __launch_bounds__(256) void scan_apply_kernel(const uint64_t *a, uint64_t len, const uint64_t *sums,
                                                          uint64_t *out)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-    uint64_t v[kScanItems];
-    uint64_t s = 0;
+    // item j of the tile at LDS word j + j / 16 (thread t's 16 items spread
+    // over the banks)
+    __shared__ uint64_t s_t[kScanTile + kScanTile / kScanItems];
+    const uint32_t t = threadIdx.x;
+    const uint64_t tb = (uint64_t)blockIdx.x * kScanTile;
 #pragma unroll
     for (uint32_t i = 0; i < kScanItems; ++i) {
-        v[i] = base + i < len ? a[base + i] : 0;
-        s += v[i];
+        const uint32_t j = 256 * i + t;
+        s_t[j + j / kScanItems] = tb + j < len ? a[tb + j] : 0;
     }
+    __syncthreads();
+    const uint32_t p0 = t * (kScanItems + 1);
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanItems; ++i) s += s_t[p0 + i];
     uint64_t total;
     uint64_t run = block256_excl_scan(s, total) + sums[blockIdx.x];
 #pragma unroll
     for (uint32_t i = 0; i < kScanItems; ++i) {
-        if (base + i < len) out[base + i] = run;
-        run += v[i];
+        const uint64_t v = s_t[p0 + i];
+        s_t[p0 + i] = run;
+        run += v;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = sums[gridDim.x];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t i = 0; i < kScanItems; ++i) {
+        const uint32_t j = 256 * i + t;
+        if (tb + j < len) out[tb + j] = s_t[j + j / kScanItems];
+    }
+    if (blockIdx.x == 0 && t == 0) out[len] = sums[gridDim.x];
 }
 
 // ---------------------------------------------------------------------------
