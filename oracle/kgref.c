@@ -77,7 +77,7 @@ void kgref_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t o
  * (Sec. 2.2: one seed per recursion subtree, independent of the PE). */
 enum { TAG_DTREE = 1, TAG_UTREE = 2, TAG_CBIN = 3, TAG_TTREE = 4, TAG_TLEAF = 5, TAG_INST = 6, TAG_SKIP = 7 };
 
-/* A stream is Philox keyed by the seed with counter (j, a, b, tag);
+/* A stream is Philox keyed by the seed with counter (a, j, b, tag);
  * j counts 128-bit blocks. */
 typedef struct {
     uint32_t key[2];
@@ -98,7 +98,7 @@ static void stream_init(stream_t *s, uint64_t seed, uint32_t a, uint32_t b, uint
 
 static void stream_block(stream_t *s, uint64_t j, uint32_t out[4])
 {
-    uint32_t ctr[4] = { (uint32_t)j, s->a, s->b, s->tag };
+    uint32_t ctr[4] = { s->a, (uint32_t)j, s->b, s->tag };
     kgref_philox(ctr, s->key, out);
 }
 

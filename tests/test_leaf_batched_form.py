@@ -11,9 +11,10 @@ import pytest
 
 
 def philox_words(kgref, seed, ordinal, tile, nblocks):
+    # counter (ordinal, block, tile, TLEAF)
     rec = np.zeros((nblocks, 6), dtype=np.uint32)
-    rec[:, 0] = np.arange(nblocks, dtype=np.uint32)
-    rec[:, 1] = ordinal
+    rec[:, 0] = ordinal
+    rec[:, 1] = np.arange(nblocks, dtype=np.uint32)
     rec[:, 2] = tile
     rec[:, 3] = kgref.TAG_TLEAF
     rec[:, 4] = seed & 0xFFFFFFFF

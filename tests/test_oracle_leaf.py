@@ -50,11 +50,12 @@ def test_leaf_position_marginals_uniform(kgref):
 
 def test_leaf_stream_definition_first_draws(kgref):
     """Without repeats and rejections the first k masked words are the sample:
-    draw t is word t mod 4 of block t/4 of stream (seed, ordinal, tile, TLEAF)."""
+    draw t is word t mod 4 of block t/4 of stream (seed, ordinal, tile, TLEAF):
+    Philox counter (ordinal, t/4, tile, TLEAF)."""
     S, k, seed, o, t = 2**30, 9, 12345, 17, 4
     words = []
     for j in range(3):
-        words += [int(w) for w in kgref.philox([j, o, t, kgref.TAG_TLEAF], [seed & 0xFFFFFFFF, seed >> 32])]
+        words += [int(w) for w in kgref.philox([o, j, t, kgref.TAG_TLEAF], [seed & 0xFFFFFFFF, seed >> 32])]
     want = sorted(w & (S - 1) for w in words[:k])
     assert len(set(want)) == k
     assert [int(x) for x in kgref.leaf(k, S, seed, o, t)] == want
