@@ -158,7 +158,7 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
  * bits (Sec. 2.1.1, 4.3): each 2^s-slot tile of each chunk runs its Bernoulli
  * trials by waiting times, floor(log U / log(1 - p)) failures before the next
  * success (for p > 1/2: the waiting times of the failures), one 64-bit draw
- * of Philox counter (draw/2, chunk ordinal, tile, 7) per gap; a count pass,
+ * of Philox counter (chunk ordinal, draw/2, tile, 7) per gap; a count pass,
  * a scan of the tile counts and a write pass.  Output order and arguments as
  * kg_gnp: the total goes to d_total (device, may be NULL); if it exceeds
  * capacity_edges nothing is written. */
@@ -184,8 +184,8 @@ kg_status kg_pe_view(const kg_instance *inst, uint32_t rank, uint32_t *d_edges, 
  * 2^-L, L the largest level <= 14 with 2^L r <= 1 and 4^L <= n (cells of
  * side >= max(r, n^-1/2), Sec. 5); the points per cell come from a
  * quadrant recursion of three Bin(k, 1/2) variates per node, keyed by the
- * node (Philox counter (j, Morton index, 3 level + slot, 8), Sec. 5.1); the
- * points of a cell from counter (j, cell, 0, 9); the edges from a count
+ * node (Philox counter (Morton index, j, 3 level + slot, 8), Sec. 5.1); the
+ * points of a cell from counter (cell, j, 0, 9); the edges from a count
  * pass, a scan and a write pass over each point's cell and its eight
  * neighbours (Sec. 5.3).  The output does not depend on any launch setting.
  *   d_points  device, n x (double x, double y), 16-byte aligned, written in
@@ -210,11 +210,11 @@ kg_status kg_rgg2d(uint64_t n, double r, uint64_t seed, double *d_points, uint32
  * two points at distance below r.  The cube is cut into 8^L cells of side
  * 2^-L, L the largest level <= 10 with 2^L r <= 1 and 8^L <= n; the points
  * per cell come from an octant recursion of seven Bin(k, 1/2) variates per
- * node (the 2^d - 1 binomials of Sec. 5.1; Philox counter (j, Morton index,
+ * node (the 2^d - 1 binomials of Sec. 5.1; Philox counter (Morton index, j,
  * 7 level + slot, 10): slot 0 the lower z half, 1 and 2 the lower y halves
  * of the lower and upper z half, 3..6 the lower x halves of the four (y, z)
  * quarters); point j of a cell takes the 64-bit draws 3j, 3j + 1, 3j + 2 of
- * counter (., cell, 0, 11) for x, y, z; the edges come from a count pass,
+ * counter (cell, ., 0, 11) for x, y, z; the edges come from a count pass,
  * a scan and a write pass over each point's cell and its 26 neighbours
  * (Sec. 5.3).  The output does not depend on any launch setting.
  *   d_points  device, n x (double x, double y, double z), 8-byte aligned,

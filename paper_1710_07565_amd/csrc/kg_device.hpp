@@ -64,22 +64,58 @@ __device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k)
     return r;
 }
 
-__device__ __forceinline__ U4 philox_uniform_key(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                                 uint32_t k1)
+// Philox4x32-10 of counter (a, j, b, tag) under a wave-uniform key, with a,
+// b and tag wave-uniform and the block j per lane: the first round's products
+// are both uniform, the second and third have one uniform product each, so
+// they are formed by the scalar unit.
+__device__ __forceinline__ U4 philox_wave(uint32_t a, uint32_t j, uint32_t b, uint32_t tag, uint32_t k0,
+                                         uint32_t k1)
 {
-    // the round keys are formed anew in every call: adding an opaque zero
-    // keeps the compiler from hoisting all twenty of them into scalar
-    // registers for a whole loop, which pushed other scalars into spills
     uint32_t z;
     asm volatile("s_mov_b32 %0, 0" : "=s"(z));
     k0 += z;
     k1 += z;
+    // round 1: c0 = a, c1 = j, c2 = b, c3 = tag
+    uint64_t p0 = (uint64_t)0xD2511F53u * a;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * b;
+    uint32_t c0 = ((uint32_t)(p1 >> 32) ^ k0) ^ j;     // lane
+    uint32_t c1 = (uint32_t)p1;                        // uniform
+    uint32_t c2 = (uint32_t)(p0 >> 32) ^ tag ^ k1;     // uniform
+    uint32_t c3 = (uint32_t)p0;                        // uniform
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    // round 2: c0 lane, c2 uniform
+    p0 = (uint64_t)0xD2511F53u * c0;
+    p1 = (uint64_t)0xCD9E8D57u * c2;
+    {
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;        // uniform
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);      // lane
+        c1 = (uint32_t)p1;                                       // uniform
+        c3 = (uint32_t)p0;                                       // lane
+        c0 = n0;
+        c2 = n2;
+    }
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    // round 3: c0 uniform, c2 lane
+    p0 = (uint64_t)0xD2511F53u * c0;
+    p1 = (uint64_t)0xCD9E8D57u * c2;
+    {
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);      // lane
+        const uint32_t n2 = c3 ^ ((uint32_t)(p0 >> 32) ^ k1);      // lane
+        c1 = (uint32_t)p1;                                       // lane
+        c3 = (uint32_t)p0;                                       // uniform
+        c0 = n0;
+        c2 = n2;
+    }
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    for (int r = 3; r < 10; ++r) {
+        p0 = (uint64_t)0xD2511F53u * c0;
+        p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t n0 = xor3_sk((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3_sk((uint32_t)(p0 >> 32), c3, k1);
+        const uint32_t n2 = r == 3 ? (uint32_t)(p0 >> 32) ^ (c3 ^ k1) : xor3_sk((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -90,14 +126,14 @@ __device__ __forceinline__ U4 philox_uniform_key(uint32_t c0, uint32_t c1, uint3
     return U4{c0, c1, c2, c3};
 }
 
-// A random stream: Philox keyed by the seed, counter (block, a, b, tag).
+// A random stream: Philox keyed by the seed, counter (a, block, b, tag).
 struct Stream {
     uint32_t k0, k1, a, b, tag;
-    __device__ __forceinline__ U4 block(uint32_t j) const { return philox(j, a, b, tag, k0, k1); }
+    __device__ __forceinline__ U4 block(uint32_t j) const { return philox(a, j, b, tag, k0, k1); }
     // only when k0, k1 are wave-uniform (scalar registers)
     __device__ __forceinline__ U4 block_uniform_key(uint32_t j) const
     {
-        return philox_uniform_key(j, a, b, tag, k0, k1);
+        return philox_wave(a, j, b, tag, k0, k1);
     }
 };
 
