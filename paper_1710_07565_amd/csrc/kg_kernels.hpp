@@ -29,7 +29,7 @@ struct Job {
     uint64_t *bsum;          // 3 x (G / 64 rounded up): per 64 chunks the sums of
                              // off, tstart, ustart, then their exclusive prefixes
     uint64_t *tile_off;      // output offset of every tile, + total
-    uint64_t *status;        // [0] edges [1] overflow [2] tiles [3] units [4] queued tiles
+    uint64_t *status;        // [0] edges [1] overflow [2] tiles [3] units [4] queued tiles [5] tile ranges handed out
     uint64_t *queue;         // tile_cap entries: tiles left to the general base case
     uint64_t *out_total;     // optional: edge total
     uint64_t *inst_off;      // optional: ninst + 1 instance offsets
@@ -225,6 +225,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(Job job)
         const uint64_t overflow = (E > job.capacity || T > job.tile_cap) ? 1 : 0;
         job.status[0] = E; job.status[1] = overflow; job.status[2] = T; job.status[3] = U;
         job.status[4] = 0;
+        job.status[5] = 0;
         if (T <= job.tile_cap) job.tile_off[T] = E;
         if (job.out_total) *job.out_total = E;
     }

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(1024) void skip_scan_kernel(Job job, uint64_t nwave
     if (t == 0) {
         job.status[0] = carry;
         job.status[1] = carry > job.capacity ? 1 : 0;
+        job.status[5] = 0;
         if (job.out_total) *job.out_total = carry;
     }
 }
@@ -147,8 +148,9 @@ __global__ __launch_bounds__(64) void skip_fix_kernel(Job job)
     else if (t == T) job.tile_off[T] = job.status[0];
 }
 
-// Write pass: a persistent grid walks contiguous tile ranges chunk by chunk
-// (as the main sampler does, with its decoders).  The waiting times of a
+// Write pass: a persistent grid walks ranges of tiles chunk by chunk, each
+// workgroup taking the next range from the shared counter (as the main
+// sampler does, with its decoders).  The waiting times of a
 // tile are independent draws, so the positions of its events (successes, or
 // failures when p > 1/2) are prefix sums: x_d = x_{d-1} + 1 + g_d.  A round
 // takes 128 draws (lane L: block 64 r + L, draws 128 r + 2 L and + 1), forms
@@ -163,92 +165,85 @@ __global__ __launch_bounds__(64) void skip_write_kernel(Job job)
     __shared__ __attribute__((aligned(16))) uint32_t s_key[kSkipKeys];
     if (ld_uni(job.status + 1)) return;
     const uint64_t T = ld_uni(job.status + 2);
-    uint64_t t, t1;
-    tile_range(T, t, t1);
-    if (t >= t1) return;
     const double p = job.one.p;
     const bool flip = p > 0.5;
     const bool all = p >= 1.0;
     const double L = log1p_f64(flip ? -(1.0 - p) : -p);
     const uint32_t lane = threadIdx.x;
-    uint64_t g;
-    {
-        uint64_t lo = 0, hi = job.G;
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
-        }
-        g = lo;
-    }
     TileWalk w;
     TileCtx &tc = w.tc;
     tc.edges = job.edges;
-    for (;;) {
-        w.enter(job, g);
-        const uint64_t tend = w.gend < t1 ? w.gend : t1;
-        for (; t < tend; ++t) {
-            const uint64_t o0 = ld_uni(job.tile_off + t);
-            const uint64_t k = ld_uni(job.tile_off + t + 1) - o0;
-            if (k == 0) continue;
-            w.tile(t);
-            tc.st.tag = TAG_SKIP;
-            tc.o0 = o0;
-            const uint64_t S = tc.S;
-            if (all) {
-                emit_complement(tc, s_key, 0, 0, S, 0);
-                continue;
-            }
-            uint64_t pos = 0, rlo = 0, done = 0;
-            uint32_t nb = 0;
-            for (uint32_t r = 0;; ++r) {
-                const U4 q = tc.st.block_uniform_key(64 * r + lane);
-                const double U0 = unit_of(((uint64_t)q.y << 32) | q.x);
-                const double U1 = unit_of(((uint64_t)q.w << 32) | q.z);
-                const double g0 = floor(log_f64(U0) / L), g1 = floor(log_f64(U1) / L);
-                const double cap = (double)S;
-                const uint64_t a0 = (uint64_t)(g0 < cap ? g0 : cap) + 1;
-                const uint64_t a1 = (uint64_t)(g1 < cap ? g1 : cap) + 1;
-                const uint64_t sum = a0 + a1;
-                const uint64_t incl = wave_incl_scan64(sum);
-                const uint64_t x0 = pos + (incl - sum) + a0 - 1, x1 = x0 + a1;
-                const bool v0 = x0 < S, v1 = x1 < S;
-                const uint32_t nv = (uint32_t)(__popcll(__ballot(v0)) + __popcll(__ballot(v1)));
-                if (nb + nv > kSkipKeys) {
-                    // batch full: out with it (a wave-uniform decision)
-                    __syncthreads();
-                    if (!flip) {
-                        TileCtx tb = tc;
-                        tb.o0 = o0 + done;
-                        emit_tile(tb, s_key, nb);
-                        done += nb;
-                    } else {
-                        const uint64_t rhi = (uint64_t)s_key[nb - 1] + 1;
-                        done += emit_complement(tc, s_key, nb, rlo, rhi, done);
-                        rlo = rhi;
-                    }
-                    __syncthreads();
-                    nb = 0;
+    const TileGrab grab(T);
+    uint64_t t, t1;
+    while (grab.next(job, t, t1)) {
+        uint64_t g = chunk_of_tile(job, t);
+        for (;;) {
+            w.enter(job, g);
+            const uint64_t tend = w.gend < t1 ? w.gend : t1;
+            for (; t < tend; ++t) {
+                const uint64_t o0 = ld_uni(job.tile_off + t);
+                const uint64_t k = ld_uni(job.tile_off + t + 1) - o0;
+                if (k == 0) continue;
+                w.tile(t);
+                tc.st.tag = TAG_SKIP;
+                tc.o0 = o0;
+                const uint64_t S = tc.S;
+                if (all) {
+                    emit_complement(tc, s_key, 0, 0, S, 0);
+                    continue;
                 }
-                if (v0) s_key[nb + 2 * lane] = (uint32_t)x0;
-                if (v1) s_key[nb + 2 * lane + 1] = (uint32_t)x1;
-                nb += nv;
-                if (nv < 128) break;
-                pos += __builtin_amdgcn_readlane((uint32_t)incl, 63) |
-                       ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(incl >> 32), 63) << 32);
+                uint64_t pos = 0, rlo = 0, done = 0;
+                uint32_t nb = 0;
+                for (uint32_t r = 0;; ++r) {
+                    const U4 q = tc.st.block_uniform_key(64 * r + lane);
+                    const double U0 = unit_of(((uint64_t)q.y << 32) | q.x);
+                    const double U1 = unit_of(((uint64_t)q.w << 32) | q.z);
+                    const double g0 = floor(log_f64(U0) / L), g1 = floor(log_f64(U1) / L);
+                    const double cap = (double)S;
+                    const uint64_t a0 = (uint64_t)(g0 < cap ? g0 : cap) + 1;
+                    const uint64_t a1 = (uint64_t)(g1 < cap ? g1 : cap) + 1;
+                    const uint64_t sum = a0 + a1;
+                    const uint64_t incl = wave_incl_scan64(sum);
+                    const uint64_t x0 = pos + (incl - sum) + a0 - 1, x1 = x0 + a1;
+                    const bool v0 = x0 < S, v1 = x1 < S;
+                    const uint32_t nv = (uint32_t)(__popcll(__ballot(v0)) + __popcll(__ballot(v1)));
+                    if (nb + nv > kSkipKeys) {
+                        // batch full: out with it (a wave-uniform decision)
+                        __syncthreads();
+                        if (!flip) {
+                            TileCtx tb = tc;
+                            tb.o0 = o0 + done;
+                            emit_tile(tb, s_key, nb);
+                            done += nb;
+                        } else {
+                            const uint64_t rhi = (uint64_t)s_key[nb - 1] + 1;
+                            done += emit_complement(tc, s_key, nb, rlo, rhi, done);
+                            rlo = rhi;
+                        }
+                        __syncthreads();
+                        nb = 0;
+                    }
+                    if (v0) s_key[nb + 2 * lane] = (uint32_t)x0;
+                    if (v1) s_key[nb + 2 * lane + 1] = (uint32_t)x1;
+                    nb += nv;
+                    if (nv < 128) break;
+                    pos += __builtin_amdgcn_readlane((uint32_t)incl, 63) |
+                           ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(incl >> 32), 63) << 32);
+                }
+                __syncthreads();
+                if (!flip) {
+                    TileCtx tb = tc;
+                    tb.o0 = o0 + done;
+                    emit_tile(tb, s_key, nb);
+                } else {
+                    emit_complement(tc, s_key, nb, rlo, S, done);
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            if (!flip) {
-                TileCtx tb = tc;
-                tb.o0 = o0 + done;
-                emit_tile(tb, s_key, nb);
-            } else {
-                emit_complement(tc, s_key, nb, rlo, S, done);
-            }
-            __syncthreads();
+            if (t >= t1) break;
+            ++g;
+            while (ld_uni(job.tstart + g + 1) <= t) ++g;
         }
-        if (t >= t1) break;
-        ++g;
-        while (ld_uni(job.tstart + g + 1) <= t) ++g;
     }
 }
 

@@ -19,6 +19,9 @@ constexpr uint32_t kFastDraws = 1280;   // draws of one wave's base case (at mos
 constexpr uint32_t kFastRounds = 5;     // rounds of 256 draws (one Philox block per lane each)
 constexpr uint32_t kKeyWords = 1288;    // LDS key words: >= kFastDraws + 3 and >= the widest sort span (64 x 20)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint64_t kGrabBig = 32;       // tiles per range a workgroup takes from the shared counter ...
+constexpr uint64_t kGrabSmall = 8;      // ... and near the end of the walk
+constexpr uint64_t kTailTiles = 64;     // tiles per workgroup handed out in small ranges
 
 // Wave-uniform 64-bit load through the scalar data cache.  Only for data
 // that no lane writes while the kernel runs (sizes and offsets written by
@@ -27,6 +30,62 @@ __device__ __forceinline__ uint64_t ld_uni(const uint64_t *p)
 {
     return *(const __attribute__((address_space(4))) uint64_t *)p;
 }
+
+// The chunk of tile t (wave-uniform): the last g with tstart[g] <= t.  A
+// 64-way search: at each level the lanes probe 64 evenly spaced entries of
+// the candidate range and the count of those <= t (a prefix of the lanes,
+// the starts being sorted) picks the sub-range, so the wave waits for
+// ceil(log64 G) loads, not log2 G.  Keeps tstart[lo] <= t (tstart[0] = 0).
+__device__ __forceinline__ uint64_t chunk_of_tile(const Job &job, uint64_t t)
+{
+    const uint64_t lane = threadIdx.x & 63;
+    uint64_t lo = 0, n = job.G;
+    while (n > 1) {
+        const uint64_t step = (n + 63) >> 6;
+        const uint64_t p = lo + lane * step;
+        const bool le = p < lo + n && job.tstart[p] <= t;
+        const uint64_t c = (uint64_t)__popcll(__ballot(le));   // >= 1: lane 0 probes lo
+        const uint64_t end = lo + n;
+        lo += (c - 1) * step;
+        n = end - lo < step ? end - lo : step;
+    }
+    return lo;
+}
+
+// Ranges of tiles for a persistent grid, handed out in tile order by the
+// counter status[5] (cleared by the scan kernel): a workgroup that is done
+// with its range takes the next one, so none waits on a slow tail.  Ranges
+// of kGrabBig tiles first, then, for the last kTailTiles tiles per
+// workgroup of the grid, ranges of kGrabSmall, so that the walk ends evenly
+// and the counter, the chunk search and the chunk set-up are paid once per
+// kGrabBig tiles for most of it.
+struct TileGrab {
+    uint64_t T, head, qh;   // tiles, tiles handed out in large ranges, their number of ranges
+
+    __device__ __forceinline__ TileGrab(uint64_t tiles)
+    {
+        T = tiles;
+        const uint64_t tail = (uint64_t)gridDim.x * kTailTiles;
+        head = T > tail ? T - tail : 0;
+        qh = (head + kGrabBig - 1) / kGrabBig;
+    }
+
+    // the next range [t0, t1); false once every tile has been handed out
+    __device__ __forceinline__ bool next(const Job &job, uint64_t &t0, uint64_t &t1) const
+    {
+        uint64_t b = 0;
+        if (threadIdx.x == 0) b = atomicAdd((unsigned long long *)(job.status + 5), 1ull);
+        const uint64_t q = uni64(b);
+        if (q < qh) {
+            t0 = q * kGrabBig;
+            t1 = t0 + kGrabBig < head ? t0 + kGrabBig : head;
+        } else {
+            t0 = head + (q - qh) * kGrabSmall;
+            t1 = t0 + kGrabSmall < T ? t0 + kGrabSmall : T;
+        }
+        return t0 < T;
+    }
+};
 
 // The chunk a wave is in: chunk constants, the stream and the decoder of
 // its tiles (enter), the chunk of a tile (locate) and the context of one
@@ -86,16 +145,8 @@ struct TileWalk {
         tc.st = Stream{uni((uint32_t)I.seed), uni((uint32_t)(I.seed >> 32)), c, 0, TAG_TLEAF};
     }
 
-    // the chunk of tile t (last g with tstart[g] <= t), entered
-    __device__ __forceinline__ void locate(const Job &job, uint64_t t)
-    {
-        uint64_t lo = 0, hi = job.G;
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
-        }
-        enter(job, lo);
-    }
+    // the chunk of tile t, entered
+    __device__ __forceinline__ void locate(const Job &job, uint64_t t) { enter(job, chunk_of_tile(job, t)); }
 
     // slot count, stream counter and decoding constants of tile t (of the
     // current chunk)
@@ -497,15 +548,6 @@ __device__ __forceinline__ void emit_tile(const TileCtx &t, const uint32_t *s, u
     }
 }
 
-// Blocked tile range of workgroup blockIdx.x among gridDim.x.
-__device__ __forceinline__ void tile_range(uint64_t T, uint64_t &t0, uint64_t &t1)
-{
-    const uint64_t W = gridDim.x;
-    const uint64_t per = (T + W - 1) / W;
-    t0 = (uint64_t)blockIdx.x * per;
-    t1 = t0 + per < T ? t0 + per : T;
-}
-
 // 5 waves per SIMD: the LDS of a wave (keys of up to 1280 draws and 512
 // bucket counters, 7.2 KB) allows no more, and leaves 102 VGPRs
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void tile_kernel(Job job)
@@ -514,9 +556,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // bucket counters, then starts
     if (ld_uni(job.status + 1)) return;
     const uint64_t T = ld_uni(job.status + 2);
-    uint64_t t, t1;
-    tile_range(T, t, t1);
-    if (t >= t1) return;
     {
         uint4 *cw = reinterpret_cast<uint4 *>(s_cnt) + 2 * threadIdx.x;
         cw[0] = make_uint4(0, 0, 0, 0);
@@ -524,85 +563,80 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
         __syncthreads();
     }
     const uint32_t lim = job.fast_cap < kFastDraws ? job.fast_cap : kFastDraws;
-    // chunk of the first tile: last g with tstart[g] <= t
-    uint64_t g;
-    {
-        uint64_t lo = 0, hi = job.G;
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (ld_uni(job.tstart + mid) <= t) lo = mid; else hi = mid;
-        }
-        g = lo;
-    }
-    // tile offsets are read two tiles ahead: they come from HBM (the output
-    // stream evicts them from the caches), so a tile never waits for its own
-    uint64_t o_next = ld_uni(job.tile_off + t);
-    uint64_t o_pre = ld_uni(job.tile_off + t + 1);
     TileWalk w;
     TileCtx &tc = w.tc;
     Decoder &d = tc.dec;
     tc.edges = job.edges;
-    for (;;) {
-        // chunk constants, then the decoder at the wave's first tile of the chunk
-        w.enter(job, g);
-        const uint64_t tend = w.gend < t1 ? w.gend : t1;
-        const uint32_t s = w.s;
-        const uint64_t full_S = 1ull << s;
-        uint64_t lstart = (t - w.gstart) << s;
-        if (d.type != 2) {
-            const uint64_t q = lstart / d.dv;
-            d.c0 = uni((uint32_t)(lstart - q * d.dv));
-            d.r0 = uni(w.row0 + (uint32_t)q);
-        }
-        const uint32_t qs32 = (uint32_t)w.qs;
-        for (; t < tend; ++t) {
-            const uint64_t o0 = o_next;
-            o_next = o_pre;
-            if (t + 2 <= T) o_pre = ld_uni(job.tile_off + t + 2);
-            const uint64_t k = o_next - o0;
-            if (k != 0) {
-                // slots of the tile: 2^s except for the chunk's last tile
-                if (t + 1 < w.gend) {
-                    tc.S = full_S;
-                    tc.bits = s;
-                    tc.mask = s >= 32 ? 0xFFFFFFFFu : (1u << s) - 1;
-                    tc.full = 1;
-                } else {
-                    tc.S = uni64(w.N - lstart);
-                    tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
-                    tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
-                    tc.full = uni(tc.S == (1ull << tc.bits));
-                }
-                tc.st.b = uni((uint32_t)(t - w.gstart));
-                d.lbase = lstart;
-                d.wide = s == 32 ? uni((uint64_t)d.c0 + tc.S > (1ull << 32)) : 0u;
-                tc.o0 = o0;
-                const bool comp = 2 * k > tc.S;
-                const uint64_t ke = comp ? tc.S - k : k;
-                if (ke == 0) {
-                    emit_complement(tc, s_key, 0, 0, tc.S, 0);
-                } else if (ke <= lim && fast_set(tc, s_key, s_cnt, (uint32_t)ke, lim)) {
-                    if (!comp) emit_tile(tc, s_key, (uint32_t)ke);
-                    else emit_complement(tc, s_key, (uint32_t)ke, 0, tc.S, 0);
-                } else if (threadIdx.x == 0) {
-                    const uint64_t q = atomicAdd((unsigned long long *)(job.status + 4), 1ull);
-                    job.queue[q] = t;
-                }
-                __syncthreads();
-            }
-            // next tile of the chunk: 2^s = qs dv + rs slots further
-            lstart += full_S;
+    const TileGrab grab(T);
+    uint64_t t, t1;
+    while (grab.next(job, t, t1)) {
+        uint64_t g = chunk_of_tile(job, t);
+        // tile offsets are read two tiles ahead: they come from HBM (the output
+        // stream evicts them from the caches), so a tile never waits for its own
+        uint64_t o_next = ld_uni(job.tile_off + t);
+        uint64_t o_pre = ld_uni(job.tile_off + t + 1);
+        for (;;) {
+            // chunk constants, then the decoder at the wave's first tile of the chunk
+            w.enter(job, g);
+            const uint64_t tend = w.gend < t1 ? w.gend : t1;
+            const uint32_t s = w.s;
+            const uint64_t full_S = 1ull << s;
+            uint64_t lstart = (t - w.gstart) << s;
             if (d.type != 2) {
-                uint32_t c0 = d.c0 + w.rs, r0 = d.r0 + qs32;
-                if (c0 >= d.dv) { c0 -= d.dv; ++r0; }
-                d.c0 = c0;
-                d.r0 = r0;
+                const uint64_t q = lstart / d.dv;
+                d.c0 = uni((uint32_t)(lstart - q * d.dv));
+                d.r0 = uni(w.row0 + (uint32_t)q);
             }
+            const uint32_t qs32 = (uint32_t)w.qs;
+            for (; t < tend; ++t) {
+                const uint64_t o0 = o_next;
+                o_next = o_pre;
+                if (t + 2 <= T) o_pre = ld_uni(job.tile_off + t + 2);
+                const uint64_t k = o_next - o0;
+                if (k != 0) {
+                    // slots of the tile: 2^s except for the chunk's last tile
+                    if (t + 1 < w.gend) {
+                        tc.S = full_S;
+                        tc.bits = s;
+                        tc.mask = s >= 32 ? 0xFFFFFFFFu : (1u << s) - 1;
+                        tc.full = 1;
+                    } else {
+                        tc.S = uni64(w.N - lstart);
+                        tc.bits = uni(tc.S <= 1 ? 0 : 64 - __clzll(tc.S - 1));
+                        tc.mask = uni(tc.bits >= 32 ? 0xFFFFFFFFu : ((1u << tc.bits) - 1));
+                        tc.full = uni(tc.S == (1ull << tc.bits));
+                    }
+                    tc.st.b = uni((uint32_t)(t - w.gstart));
+                    d.lbase = lstart;
+                    d.wide = s == 32 ? uni((uint64_t)d.c0 + tc.S > (1ull << 32)) : 0u;
+                    tc.o0 = o0;
+                    const bool comp = 2 * k > tc.S;
+                    const uint64_t ke = comp ? tc.S - k : k;
+                    if (ke == 0) {
+                        emit_complement(tc, s_key, 0, 0, tc.S, 0);
+                    } else if (ke <= lim && fast_set(tc, s_key, s_cnt, (uint32_t)ke, lim)) {
+                        if (!comp) emit_tile(tc, s_key, (uint32_t)ke);
+                        else emit_complement(tc, s_key, (uint32_t)ke, 0, tc.S, 0);
+                    } else if (threadIdx.x == 0) {
+                        const uint64_t q = atomicAdd((unsigned long long *)(job.status + 4), 1ull);
+                        job.queue[q] = t;
+                    }
+                    __syncthreads();
+                }
+                // next tile of the chunk: 2^s = qs dv + rs slots further
+                lstart += full_S;
+                if (d.type != 2) {
+                    uint32_t c0 = d.c0 + w.rs, r0 = d.r0 + qs32;
+                    if (c0 >= d.dv) { c0 -= d.dv; ++r0; }
+                    d.c0 = c0;
+                    d.r0 = r0;
+                }
+            }
+            if (t >= t1) break;
+            // next chunk that has tiles
+            ++g;
+            while (ld_uni(job.tstart + g + 1) <= t) ++g;
         }
-        if (t >= t1) break;
-        // next chunk that has tiles
-        ++g;
-        while (ld_uni(job.tstart + g + 1) <= t) ++g;
     }
 }
 

@@ -128,5 +128,6 @@ def test_rgg2d_fullsize_sampled(kgref):
         cand = np.array(sorted(v for v in cand if v > u), dtype=np.int64)
         d = Ph[cand] - Ph[u]
         want = cand[d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] < r * r]
-        lo, hi = np.searchsorted(col0, u, "left"), np.searchsorted(col0, u, "right")
+        # a query of the column's own dtype: no cast of the whole column per call
+        lo, hi = np.searchsorted(col0, np.uint32(u), "left"), np.searchsorted(col0, np.uint32(u), "right")
         assert np.array_equal(Eh[lo:hi, 1].astype(np.int64), want), int(u)
