@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64) void skip_write_kernel(Job job)
     TileWalk w;
     TileCtx &tc = w.tc;
     tc.edges = job.edges;
-    const TileGrab grab(T);
+    TileGrab grab(T);
     uint64_t t, t1;
     while (grab.next(job, t, t1)) {
         uint64_t g = chunk_of_tile(job, t);

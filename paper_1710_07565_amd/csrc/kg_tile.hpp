@@ -52,38 +52,59 @@ __device__ __forceinline__ uint64_t chunk_of_tile(const Job &job, uint64_t t)
     return lo;
 }
 
-// Ranges of tiles for a persistent grid, handed out in tile order by the
-// counter status[5] (cleared by the scan kernel): a workgroup that is done
-// with its range takes the next one, so none waits on a slow tail.  Ranges
-// of kGrabBig tiles first, then, for the last kTailTiles tiles per
-// workgroup of the grid, ranges of kGrabSmall, so that the walk ends evenly
-// and the counter, the chunk search and the chunk set-up are paid once per
-// kGrabBig tiles for most of it.
+// Ranges of tiles for a persistent grid, in tile order: workgroup b takes
+// range b first, then the next one not yet handed out, from the counter
+// status[5] (cleared by the scan kernel), so a workgroup whose tiles were
+// cheap takes more and none waits on a slow tail.  Ranges of kGrabBig tiles
+// first, then, for the last kTailTiles tiles per workgroup of the grid,
+// ranges of kGrabSmall, so that the walk ends evenly and the counter, the
+// chunk search and the chunk set-up are paid once per kGrabBig tiles for
+// most of it.  Walks with fewer than 4 x kGrabBig tiles per workgroup take
+// smaller ranges (down to one tile) so that small jobs still spread over the
+// grid; when the grid holds every range, no workgroup touches the counter.
 struct TileGrab {
-    uint64_t T, head, qh;   // tiles, tiles handed out in large ranges, their number of ranges
+    uint64_t T, head, qh, Q;   // tiles, tiles in large ranges, large ranges, all ranges
+    uint64_t big, small;       // range sizes
+    bool first;
 
     __device__ __forceinline__ TileGrab(uint64_t tiles)
     {
         T = tiles;
-        const uint64_t tail = (uint64_t)gridDim.x * kTailTiles;
+        const uint64_t W = gridDim.x;
+        const uint64_t fair = T / (4 * W);
+        small = fair >= kGrabSmall ? kGrabSmall : fair > 0 ? fair : 1;
+        big = fair >= kGrabBig ? kGrabBig : fair > small ? fair : small;
+        const uint64_t tail = W * kTailTiles;
         head = T > tail ? T - tail : 0;
-        qh = (head + kGrabBig - 1) / kGrabBig;
+        qh = (head + big - 1) / big;
+        Q = qh + (T - head + small - 1) / small;
+        first = true;
     }
 
-    // the next range [t0, t1); false once every tile has been handed out
-    __device__ __forceinline__ bool next(const Job &job, uint64_t &t0, uint64_t &t1) const
+    // the next range [t0, t1); false once every range has been handed out
+    __device__ __forceinline__ bool next(const Job &job, uint64_t &t0, uint64_t &t1)
     {
-        uint64_t b = 0;
-        if (threadIdx.x == 0) b = atomicAdd((unsigned long long *)(job.status + 5), 1ull);
-        const uint64_t q = uni64(b);
-        if (q < qh) {
-            t0 = q * kGrabBig;
-            t1 = t0 + kGrabBig < head ? t0 + kGrabBig : head;
+        const uint64_t W = gridDim.x;
+        uint64_t q;
+        if (first) {
+            q = blockIdx.x;
+            first = false;
+        } else if (Q <= W) {
+            return false;
         } else {
-            t0 = head + (q - qh) * kGrabSmall;
-            t1 = t0 + kGrabSmall < T ? t0 + kGrabSmall : T;
+            uint64_t b = 0;
+            if (threadIdx.x == 0) b = atomicAdd((unsigned long long *)(job.status + 5), 1ull);
+            q = W + uni64(b);
         }
-        return t0 < T;
+        if (q >= Q) return false;
+        if (q < qh) {
+            t0 = q * big;
+            t1 = t0 + big < head ? t0 + big : head;
+        } else {
+            t0 = head + (q - qh) * small;
+            t1 = t0 + small < T ? t0 + small : T;
+        }
+        return true;
     }
 };
 
@@ -548,9 +569,9 @@ __device__ __forceinline__ void emit_tile(const TileCtx &t, const uint32_t *s, u
     }
 }
 
-// 5 waves per SIMD: the LDS of a wave (keys of up to 1280 draws and 512
-// bucket counters, 7.2 KB) allows no more, and leaves 102 VGPRs
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void tile_kernel(Job job)
+// 4 waves per SIMD (up to 128 VGPRs, no spills); the LDS of a wave (keys of
+// up to 1280 draws and 512 bucket counters, 7.2 KB) would allow 5
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void tile_kernel(Job job)
 {
     __shared__ __attribute__((aligned(16))) uint32_t s_key[kKeyWords];
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[kBucketWords];   // bucket counters, then starts
@@ -567,7 +588,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
     TileCtx &tc = w.tc;
     Decoder &d = tc.dec;
     tc.edges = job.edges;
-    const TileGrab grab(T);
+    TileGrab grab(T);
     uint64_t t, t1;
     while (grab.next(job, t, t1)) {
         uint64_t g = chunk_of_tile(job, t);
