@@ -18,7 +18,9 @@ import json
 
 from . import _lib
 
-DEFAULT_SAMPLE_WAVES = (0, 4, 5, 6)
+# sampler workgroups (one wave each) per compute unit; 0 = as many as are
+# resident (16: 4 per SIMD); 20 puts a few past the resident ones
+DEFAULT_SAMPLE_WAVES = (0, 8, 12, 20)
 DEFAULT_PLAN_WAVES = (0, 4, 8, 16)
 DEFAULT_LEAF_CAP = (0, 768)
 
