@@ -161,10 +161,20 @@ kg_status kg_batch(const kg_instance *h_inst, uint32_t count, uint32_t *d_arena,
  * of Philox counter (chunk ordinal, draw/2, tile, 7) per gap; a count pass,
  * a scan of the tile counts and a write pass.  Output order and arguments as
  * kg_gnp: the total goes to d_total (device, may be NULL); if it exceeds
- * capacity_edges nothing is written. */
+ * capacity_edges nothing is written.  The workspace needs at least
+ * kg_workspace_bytes of the G(n,p) instance; with at least
+ * kg_gnp_skip_workspace_bytes (or none passed: the library allocates that
+ * much) a call that writes edges keeps each tile's event positions from the
+ * count pass in the workspace and the write pass only decodes them (the
+ * same bytes, each gap's logarithm computed once). */
 kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks,
                       uint32_t *d_edges, uint64_t capacity_edges, uint64_t *d_total,
                       void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Workspace bytes with which kg_gnp_skip keeps the event positions (about 5.6
+ * KB per tile of up to 1408 events: the chunk layout plus one row of 32-bit
+ * tile-local positions per tile).  Host only. */
+kg_status kg_gnp_skip_workspace_bytes(uint64_t n, double p, int directed, uint32_t chunks, uint64_t *bytes);
 
 /* The per-PE view of one instance (inst->flags must be 0): the edges
  * incident to section `rank` (< chunks), i.e. what processing element `rank`
@@ -278,8 +288,10 @@ enum {
     KG_OPT_SAMPLE_WAVES = 2,    /* resident sampler waves per compute unit (1..32) */
     KG_OPT_PLAN_WAVES = 3,      /* resident tile-planner waves per compute unit (1..64) */
     KG_OPT_TIME_KERNELS = 4,    /* 1: bracket every kernel launch with hipEvents (not under capture) */
-    KG_OPT_COUNT_LANES = 5      /* lanes per chunk in the count kernel (1, 2, 4 or 8; 0: the most for
+    KG_OPT_COUNT_LANES = 5,     /* lanes per chunk in the count kernel (1, 2, 4 or 8; 0: the most for
                                    which every workgroup of the launch is resident at once) */
+    KG_OPT_SKIP_ROW = 6         /* kg_gnp_skip: positions kept per tile (64..1408; tiles with more
+                                   events are generated again in the write pass) */
 };
 kg_status kg_set_option(int option, int64_t value);
 int64_t kg_get_option(int option);

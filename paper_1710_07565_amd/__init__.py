@@ -273,6 +273,10 @@ def gnp_skip(n, p, directed=True, seed=1, chunks=1, out=None, total=None, worksp
     torch = _torch()
     inst = Instance(n, GNP, directed, 0, p, seed, chunks)
     with _on(stream):
+        if workspace is None:
+            # room for the count pass's event positions (see gnp_skip_workspace_bytes)
+            workspace = torch.empty(gnp_skip_workspace_bytes(n, p, directed, chunks), dtype=torch.uint8,
+                                    device=device if out is None else out.device)
         ws, need = _workspace([inst], workspace, device if out is None else out.device)
         if total is None:
             total = torch.zeros(1, dtype=torch.uint64, device=ws.device)
@@ -292,6 +296,17 @@ def gnp_skip(n, p, directed=True, seed=1, chunks=1, out=None, total=None, worksp
     if sized:
         return out
     return out, total
+
+
+def gnp_skip_workspace_bytes(n, p, directed=True, chunks=1):
+    """Workspace bytes with which gnp_skip keeps the count pass's event
+    positions (one row of 32-bit positions per tile), so that the write pass
+    only decodes them; a workspace of workspace_bytes() also works, with the
+    write pass generating the events again."""
+    b = ctypes.c_uint64(0)
+    _lib.check(_lib.lib().kg_gnp_skip_workspace_bytes(int(n), float(p), int(bool(directed)), int(chunks),
+                                                      ctypes.byref(b)), "kg_gnp_skip_workspace_bytes")
+    return int(b.value)
 
 
 def rgg2d_workspace_bytes(n, r):

@@ -13,10 +13,12 @@ KG_OPT_LEAF_CAP, KG_OPT_SAMPLE_WAVES, KG_OPT_PLAN_WAVES = 1, 2, 3
 
 EXPORTS = ["kg_spec_version", "kg_strerror", "kg_workspace_bytes", "kg_set_workspace", "kg_gnm", "kg_gnp", "kg_gnp_count",
            "kg_chunk_counts", "kg_batch", "kg_batch_upload", "kg_batch_launch", "kg_pe_view", "kg_gnp_skip",
+           "kg_gnp_skip_workspace_bytes",
            "kg_rgg2d_workspace_bytes", "kg_rgg2d", "kg_rgg3d_workspace_bytes", "kg_rgg3d", "kg_instance_seed", "kg_set_option", "kg_get_option", "kg_last_hip_error", "kg_eval",
            "kg_kernel_time_read", "kg_edge_hash", "kg_gnm_static"]
 KG_OPT_TIME_KERNELS = 4
 KG_OPT_COUNT_LANES = 5
+KG_OPT_SKIP_ROW = 6
 KG_KERNEL_COUNT, KG_KERNEL_SCAN, KG_KERNEL_PLAN, KG_KERNEL_SAMPLE, KG_KERNEL_QUEUE = 0, 1, 2, 3, 4
 KG_EVAL_PHILOX, KG_EVAL_LOG, KG_EVAL_LOG1P, KG_EVAL_LNF_DIFF, KG_EVAL_HYP, KG_EVAL_BIN, KG_EVAL_SQRT_DIV = range(1, 8)
 
@@ -76,6 +78,8 @@ def lib():
     L.kg_pe_view.argtypes = [ip, u32, vp, u64, vp, vp, u64, vp]; L.kg_pe_view.restype = i32
     L.kg_gnp_skip.argtypes = [u64, dbl, ctypes.c_int, u64, u32, vp, u64, vp, vp, u64, vp]
     L.kg_gnp_skip.restype = i32
+    L.kg_gnp_skip_workspace_bytes.argtypes = [u64, dbl, ctypes.c_int, u32, vp]
+    L.kg_gnp_skip_workspace_bytes.restype = i32
     L.kg_rgg2d_workspace_bytes.argtypes = [u64, dbl, vp]; L.kg_rgg2d_workspace_bytes.restype = i32
     L.kg_rgg2d.argtypes = [u64, dbl, u64, vp, vp, u64, vp, vp, u64, vp]; L.kg_rgg2d.restype = i32
     L.kg_rgg3d_workspace_bytes.argtypes = [u64, dbl, vp]; L.kg_rgg3d_workspace_bytes.restype = i32

@@ -42,6 +42,7 @@ int64_t g_leaf_cap = 0;        // 0: default
 int64_t g_sample_waves = 0;    // per CU
 int64_t g_plan_waves = 0;      // per CU
 int64_t g_count_lanes = 0;     // lanes per chunk in the count kernel (0: chosen per call)
+int64_t g_skip_row = 0;        // positions kept per tile by kg_gnp_skip (0: kSkipKeys)
 
 // The HIP error behind the most recent KG_EDEVICE from a launch on this
 // thread (kg_last_hip_error).
@@ -139,6 +140,8 @@ kg_status capture_check(hipStream_t s, const void *d_ws)
 int g_sample_blocks_per_cu[64];
 int g_plan_blocks_per_cu[64];
 int g_skip_blocks_per_cu[64];
+int g_gen_blocks_per_cu[64];
+int g_emit_blocks_per_cu[64];
 int g_queue_blocks_per_cu[64];
 constexpr int kCountVariants = 4;   // count kernel with 1, 2, 4, 8 lanes per chunk
 int g_count_blocks_per_cu[64][kCountVariants];
@@ -164,6 +167,12 @@ kg_status ensure_init(int *dev_out)
     nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, skip_write_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
     g_skip_blocks_per_cu[dev] = nb;
+    nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, skip_gen_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    g_gen_blocks_per_cu[dev] = nb;
+    nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, skip_emit_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    g_emit_blocks_per_cu[dev] = nb;
     nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, queue_kernel<kCapMax>, 64, 0) != hipSuccess || nb < 1) nb = 1;
     g_queue_blocks_per_cu[dev] = nb;
@@ -743,6 +752,22 @@ kg_status kg_pe_view(const kg_instance *inst, uint32_t rank, uint32_t *d_edges, 
                nullptr, nullptr);
 }
 
+// Workspace of kg_gnp_skip's position rows: the chunk layout, then one row
+// of kSkipKeys 32-bit positions per tile (tile bound Tb).
+uint64_t skip_rows_offset(const Prepared &P) { return align256(P.L.total); }
+uint64_t skip_rows_bytes(const Prepared &P) { return skip_rows_offset(P) + P.Tb * (uint64_t)kSkipKeys * 4; }
+
+kg_status kg_gnp_skip_workspace_bytes(uint64_t n, double p, int directed, uint32_t chunks, uint64_t *bytes)
+{
+    if (!bytes) return KG_EINVAL;
+    const kg_instance I = make_inst(n, KG_GNP, directed, 0, p, 1, chunks);
+    Prepared P;
+    const kg_status st = prepare(&I, 1, P);
+    if (st) return st;
+    *bytes = skip_rows_bytes(P);
+    return KG_OK;
+}
+
 kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_t chunks, uint32_t *d_edges,
                       uint64_t capacity_edges, uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes,
                       void *stream)
@@ -762,8 +787,12 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
     int dev = 0;
     st = ensure_init(&dev);
     if (st) return st;
+    // a call that writes edges keeps the count pass's positions when the
+    // workspace holds a row per tile (or the library allocates it)
+    const uint64_t rows_bytes = skip_rows_bytes(P);
+    const bool rows = d_edges && (!d_workspace || workspace_bytes >= rows_bytes);
     Workspace ws;
-    st = acquire(ws, d_workspace, workspace_bytes, P.L.total, s);
+    st = acquire(ws, d_workspace, workspace_bytes, rows ? rows_bytes : P.L.total, s);
     if (st) return st;
     // the chunk and tile layout from the main path's count and offset
     // kernels; their binomial total is not this sampler's, so no capacity
@@ -771,9 +800,19 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
     Job job = make_job(P, ws, d_edges, ~0ull);
     st = launch_counts(P, job, dev, s, false);
     if (!st) {
+        uint32_t *row0 = rows ? (uint32_t *)(ws.base + skip_rows_offset(P)) : nullptr;
+        // positions kept per tile: a multiple of 4 (16-byte aligned rows)
+        const uint32_t cap = (uint32_t)opt_or(g_skip_row, kSkipKeys) & ~3u;
         {
             KernelTimer tm(KG_KERNEL_PLAN, s);
-            hipLaunchKernelGGL(skip_count_kernel, dim3((uint32_t)nw), dim3(64), 0, s, job);
+            if (rows) {
+                uint64_t ggrid = (uint64_t)g_num_cu[dev] * (uint64_t)g_gen_blocks_per_cu[dev];
+                if (ggrid > P.Tb + 1) ggrid = P.Tb + 1;
+                hipLaunchKernelGGL(skip_gen_kernel, dim3((uint32_t)ggrid), dim3(64), 0, s, job, row0, cap);
+                hipLaunchKernelGGL(skip_sums_kernel, dim3((uint32_t)nw), dim3(64), 0, s, job);
+            } else {
+                hipLaunchKernelGGL(skip_count_kernel, dim3((uint32_t)nw), dim3(64), 0, s, job);
+            }
         }
         Job jw = job;
         jw.capacity = capacity_edges;
@@ -782,9 +821,16 @@ kg_status kg_gnp_skip(uint64_t n, double p, int directed, uint64_t seed, uint32_
         hipLaunchKernelGGL(skip_fix_kernel, dim3((uint32_t)((P.Tb + 1 + 63) / 64)), dim3(64), 0, s, jw);
         {
             KernelTimer tm(KG_KERNEL_SAMPLE, s);
-            uint64_t wgrid = (uint64_t)g_num_cu[dev] * (uint64_t)g_skip_blocks_per_cu[dev];
-            if (wgrid > P.Tb + 1) wgrid = P.Tb + 1;
-            hipLaunchKernelGGL(skip_write_kernel, dim3((uint32_t)wgrid), dim3(64), 0, s, jw);
+            if (rows) {
+                uint64_t egrid = (uint64_t)g_num_cu[dev] * (uint64_t)g_emit_blocks_per_cu[dev];
+                if (egrid > P.Tb + 1) egrid = P.Tb + 1;
+                hipLaunchKernelGGL(skip_emit_kernel, dim3((uint32_t)egrid), dim3(64), 0, s, jw,
+                                   (const uint32_t *)row0, cap);
+            } else {
+                uint64_t wgrid = (uint64_t)g_num_cu[dev] * (uint64_t)g_skip_blocks_per_cu[dev];
+                if (wgrid > P.Tb + 1) wgrid = P.Tb + 1;
+                hipLaunchKernelGGL(skip_write_kernel, dim3((uint32_t)wgrid), dim3(64), 0, s, jw);
+            }
         }
         if (!launched_ok()) st = KG_EDEVICE;
     }
@@ -1050,6 +1096,10 @@ kg_status kg_set_option(int option, int64_t value)
         if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8) return KG_ERANGE;
         g_count_lanes = value;
         return KG_OK;
+    case KG_OPT_SKIP_ROW:
+        if (value != 0 && (value < 64 || value > kSkipKeys)) return KG_ERANGE;
+        g_skip_row = value;
+        return KG_OK;
     default:
         return KG_EINVAL;
     }
@@ -1107,6 +1157,7 @@ int64_t kg_get_option(int option)
     case KG_OPT_PLAN_WAVES: return g_plan_waves;
     case KG_OPT_TIME_KERNELS: return g_time_kernels;
     case KG_OPT_COUNT_LANES: return g_count_lanes;
+    case KG_OPT_SKIP_ROW: return opt_or(g_skip_row, kSkipKeys);
     default: return -1;
     }
 }

@@ -127,6 +127,27 @@ def test_generation_calls_reject_bad_arguments_without_a_device(L):
     assert L.kg_set_option(_lib.KG_OPT_COUNT_LANES, 3) == _lib.KG_ERANGE
     assert L.kg_set_option(_lib.KG_OPT_COUNT_LANES, 8) == 0 and L.kg_get_option(_lib.KG_OPT_COUNT_LANES) == 8
     assert L.kg_set_option(_lib.KG_OPT_COUNT_LANES, 0) == 0 and L.kg_get_option(_lib.KG_OPT_COUNT_LANES) == 0
+    assert L.kg_set_option(_lib.KG_OPT_SKIP_ROW, 63) == _lib.KG_ERANGE
+    assert L.kg_set_option(_lib.KG_OPT_SKIP_ROW, 1409) == _lib.KG_ERANGE
+    assert L.kg_set_option(_lib.KG_OPT_SKIP_ROW, 64) == 0 and L.kg_get_option(_lib.KG_OPT_SKIP_ROW) == 64
+    assert L.kg_set_option(_lib.KG_OPT_SKIP_ROW, 0) == 0 and L.kg_get_option(_lib.KG_OPT_SKIP_ROW) == 1408
+
+
+def test_skip_workspace_holds_a_row_per_tile(L):
+    """kg_gnp_skip_workspace_bytes: the G(n,p) workspace (rounded up to 256
+    bytes) plus 1408 32-bit positions per tile of the tile bound."""
+    from paper_1710_07565_amd import _lib
+    b = ctypes.c_uint64(0)
+    assert L.kg_gnp_skip_workspace_bytes(2**12, 0.01, 1, 8, None) == _lib.KG_EINVAL
+    assert L.kg_gnp_skip_workspace_bytes(2**12, 2.0, 1, 8, ctypes.byref(b)) == _lib.KG_EINVAL
+    for n, p, directed, P in [(2**12, 0.01, 1, 8), (2**16, 1e-4, 0, 32), (5000, 0.3516, 1, 3)]:
+        assert L.kg_gnp_skip_workspace_bytes(n, p, directed, P, ctypes.byref(b)) == 0
+        rows = b.value
+        inst = _lib.KgInstance()
+        inst.n, inst.model, inst.directed, inst.p, inst.seed, inst.chunks = n, _lib.KG_GNP, directed, p, 1, P
+        assert L.kg_workspace_bytes(ctypes.byref(inst), 1, ctypes.byref(b)) == 0
+        base = (b.value + 255) // 256 * 256
+        assert rows > base and (rows - base) % (1408 * 4) == 0
 
 
 def test_oracle_tile_exponent_is_minimal(kgref):

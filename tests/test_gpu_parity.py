@@ -134,19 +134,26 @@ def test_leaf_capacity_does_not_change_bits(kg, kgref, cap):
 
 @pytest.mark.parametrize("sw,pw", [(1, 1), (3, 2), (32, 64)])
 def test_launch_shape_does_not_change_bits(kg, sw, pw):
-    """The tile -> workgroup mapping must not show in the output."""
+    """The tile -> workgroup mapping must not show in the output: grids of
+    1, 3 and 32 sampler workgroups per compute unit (the last past the
+    resident ones) take the tiles in ranges of other sizes and orders (one
+    tile each, or 32 then 8 from the shared counter for the 2^15-tile job on
+    the smallest grid) and must write the same bytes."""
     base = gpu_gnm(kg, 5000, 10**6, False, 3, 33)
     base2 = gpu_gnm(kg, 2**14, 2**21, True, 4, 1)
+    base3 = gpu_gnm(kg, 2**17, 2**25, True, 8, 5)
     try:
         kg.set_option(kg._lib.KG_OPT_SAMPLE_WAVES, sw)
         kg.set_option(kg._lib.KG_OPT_PLAN_WAVES, pw)
         got = gpu_gnm(kg, 5000, 10**6, False, 3, 33)
         got2 = gpu_gnm(kg, 2**14, 2**21, True, 4, 1)
+        got3 = gpu_gnm(kg, 2**17, 2**25, True, 8, 5)
     finally:
         kg.set_option(kg._lib.KG_OPT_SAMPLE_WAVES, 0)
         kg.set_option(kg._lib.KG_OPT_PLAN_WAVES, 0)
     check_equal(got, base, "launch shape %d/%d" % (sw, pw))
     check_equal(got2, base2, "launch shape %d/%d" % (sw, pw))
+    check_equal(got3, base3, "launch shape %d/%d" % (sw, pw))
 
 
 @pytest.mark.parametrize("n,directed,P,model", [(2**16, True, 64, 0), (2**26, False, 256, 0),

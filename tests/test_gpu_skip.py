@@ -66,6 +66,33 @@ def test_skip_directed_workload(kgs, kgref):
     assert abs(E.shape[0] - N * p) < 6 * np.sqrt(N * p * (1 - p))
 
 
+@pytest.mark.parametrize("n,p,directed,P", [(5000, 0.01, False, 7), (5000, 0.3516, True, 3),
+                                             (4000, 0.5001, True, 2), (3000, 0.9, True, 2)])
+def test_skip_paths_agree(kgs, kgref, n, p, directed, P):
+    """The write pass decodes the count pass's stored positions when the
+    workspace holds a row per tile, and generates the events again when it
+    does not (a workspace of the plain G(n,p) size) or when a tile has more
+    events than its row keeps (rows of 64 here, so nearly every tile): the
+    same bytes, the oracle's, every way."""
+    import torch
+    want = kgref.skip_generate(kgref.inst(n, p=p, directed=directed, seed=4, chunks=P, model=kgref.GNP))
+    inst = kgs.Instance(n, kgs.GNP, directed, 0, p, 4, P)
+    small = torch.empty(kgs.workspace_bytes([inst]), dtype=torch.uint8, device="cuda")
+    assert small.numel() < kgs.gnp_skip_workspace_bytes(n, p, directed, P)
+    got_rows = kgs.gnp_skip(n, p, directed, 4, P)
+    got_regen = kgs.gnp_skip(n, p, directed, 4, P, workspace=small)
+    try:
+        kgs.set_option(kgs._lib.KG_OPT_SKIP_ROW, 64)
+        assert kgs.get_option(kgs._lib.KG_OPT_SKIP_ROW) == 64
+        got_short = kgs.gnp_skip(n, p, directed, 4, P)
+    finally:
+        kgs.set_option(kgs._lib.KG_OPT_SKIP_ROW, 0)
+    torch.cuda.synchronize()
+    for what, got in (("rows", got_rows), ("regenerated", got_regen), ("rows of 64", got_short)):
+        assert got.shape[0] == len(want), what
+        assert np.array_equal(to_np_u32(got), want), what
+
+
 @pytest.fixture(scope="module")
 def kgs():
     return require_gpu()
