@@ -269,7 +269,10 @@ def gnp_skip(n, p, directed=True, seed=1, chunks=1, out=None, total=None, worksp
              device="cuda"):
     """G(n,p) by geometric skips per tile (kg_gnp_skip): the same law as
     gnp(), other bits.  Without `out` a first call finds the size; with
-    `out`, returns (out, total) as gnp() does."""
+    `out`, returns (out, total) as gnp() does.  Without `workspace` one of
+    gnp_skip_workspace_bytes() is allocated, so that the write pass decodes
+    the count pass's stored event positions; a smaller one (at least
+    workspace_bytes() of the instance) makes it generate them again."""
     torch = _torch()
     inst = Instance(n, GNP, directed, 0, p, seed, chunks)
     with _on(stream):
